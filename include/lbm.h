@@ -1,0 +1,224 @@
+/*
+ * liblbm -- one D3Q19 lattice Boltzmann step with Smagorinsky relaxation,
+ * velocity-corrected (Bouzidi) bounce-back on moving spheres and voxel walls,
+ * and the momentum-exchange force/torque on every solid, for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The operation is the fluid half of the LBM-DEM coupling of Mutabaruka &
+ * Kamrin, arXiv:1703.05158: each time step the solids (DEM spheres, moving
+ * rigid walls) hand their kinematics to the fluid, the fluid performs one
+ * collide-stream step in which the lattice links cut by solid surfaces are
+ * closed by interpolated bounce-back with the moving-boundary correction
+ * (Sec. 2.3, eq. moving_boundary_velocity), and the fluid returns the
+ * hydrodynamic force and torque on every solid by momentum exchange
+ * (Sec. 2.3, force and torque equations; Sec. 2.5 for the coupled step).
+ * Streaming and BGK collision follow Sec. 2.2 (eq. Collision_step and the
+ * streaming equation), the velocity set Table 1, the equilibrium eq.
+ * (Equilibre_Maxwell_Boltzmann) and the Smagorinsky relaxation time the
+ * closing equation of Sec. 2.2, with the filter length and time step 1.
+ *
+ * Conventions shared by every call
+ *   - Lattice units (Sec. 2.2): spacing = time step = 1, c_s^2 = 1/3.
+ *   - Node (x, y, z) has linear index n = x + nx*(y + ny*z); every axis is
+ *     index-periodic; non-periodic boundaries are solid wall voxels.
+ *   - Populations are numbered as in Table 1 (opposite(i) = i +- 9).
+ *   - Host arrays are read or written only during the call (copied before
+ *     return).  Device pointers (the *_device calls) must stay valid until
+ *     the work queued on the handle's stream has run.
+ *   - Owner precedence: a node inside a wall voxel belongs to that wall;
+ *     otherwise to the lowest-index sphere whose closed ball contains it
+ *     (|p - X|^2 <= R^2, minimum image, evaluated in FP64 without fused
+ *     multiply-add); otherwise it is fluid.
+ *   - Force ordering: spheres first (index order), then walls (id order).
+ *   - Every call returns a status; nothing aborts or throws across the ABI.
+ *     Argument errors are detected on the host before any device work is
+ *     queued; lbm_last_error() gives a per-handle description.
+ *   - A handle is used by one host thread at a time.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx *lbm_handle;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_ERR_ARG = 1,       /* invalid argument (null pointer, range, size) */
+    LBM_ERR_OOM = 2,       /* device or pinned host allocation failed */
+    LBM_ERR_HIP = 3,       /* a HIP runtime call failed (text in lbm_last_error) */
+    LBM_ERR_STATE = 4,     /* call not valid in the handle's current state */
+    LBM_ERR_UNSTABLE = 5,  /* NaN/Inf or non-positive density detected by the guard */
+    LBM_ERR_CAPACITY = 6   /* more bodies or walls than the handle was created for */
+} lbm_status;
+
+/* Storage of the populations in HBM.  All three store deviations
+ * g_i = f_i - w_i rho0 from the rest state; collision math is FP32 and the
+ * force/torque sums FP64 in every mode. */
+typedef enum {
+    LBM_STORE_F32 = 0,     /* 4 bytes per population */
+    LBM_STORE_F16_DEV = 1, /* IEEE binary16 deviations, 2 bytes */
+    LBM_STORE_BF16_DEV = 2 /* bfloat16 deviations, 2 bytes */
+} lbm_storage;
+
+/* Link fraction q of Sec. 2.3.  BOUZIDI: q from the exact sphere geometry,
+ * walls at q = 1/2.  HALFWAY: q = 1/2 on every link (then both Bouzidi
+ * branches reduce to bounce-back at the link midpoint). */
+typedef enum { LBM_BB_BOUZIDI = 0, LBM_BB_HALFWAY = 1 } lbm_bb_mode;
+
+typedef struct lbm_config {
+    int32_t nx, ny, nz;        /* box in nodes, each >= 1 */
+    int32_t storage;           /* lbm_storage */
+    double tau0;               /* molecular relaxation time, > 1/2 (Sec. 2.2, eq. ViscositeLBM) */
+    double smag_c;             /* Smagorinsky constant C >= 0 (Sec. 2.2) */
+    double rho0;               /* reference density, > 0 (1 in lattice units) */
+    double body_force[3];      /* body-force density per fluid node per step (Guo forcing) */
+    int32_t bb_mode;           /* lbm_bb_mode */
+    int32_t max_bodies;        /* capacity of the sphere table, >= 0 */
+    int32_t max_walls;         /* capacity of the wall table, 0..255 */
+    int32_t nan_guard_every;   /* 0 = off; k > 0: check every k steps (syncs) */
+    void *stream;              /* hipStream_t to queue work on; NULL = null stream */
+} lbm_config;
+
+typedef struct lbm_info {
+    int64_t n_nodes;           /* nx*ny*nz */
+    int32_t n_bodies;          /* spheres of the current state's geometry */
+    int32_t n_walls;
+    int32_t storage_bytes;     /* bytes per stored population: 4 or 2 */
+    int32_t steps_done;
+    int64_t device_bytes;      /* device memory held by the handle */
+} lbm_info;
+
+/* Version of this interface: 10000*major + 100*minor + patch. */
+int32_t lbm_version(void);
+
+/* Create a handle: validates cfg, allocates two population buffers
+ * (19 * N * storage bytes each), the owner map (2 bytes per node) and the
+ * body/wall tables on the current HIP device.  *out is set only on LBM_OK.
+ * Errors: ARG (null pointer, sizes, tau0 <= 1/2, C < 0, rho0 <= 0, unknown
+ * enum, capacities), OOM, HIP. */
+lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out);
+
+/* Free every resource of the handle (waits for its queued work).  NULL is
+ * ignored.  The handle must not be used afterwards. */
+void lbm_destroy(lbm_handle h);
+
+/* Text of the last error on this handle ("" if none; static text if h is
+ * NULL).  Valid until the next call on the handle. */
+const char *lbm_last_error(lbm_handle h);
+
+/* Queue the handle's future work on another stream (hipStream_t or NULL). */
+lbm_status lbm_set_stream(lbm_handle h, void *stream);
+
+/* Static wall voxels (the moving rigid walls of Sec. 2.1/2.3 realised as
+ * voxel objects whose links close at q = 1/2).
+ *   wall_id  : N bytes, 0 = not a wall, 1..n_walls = wall object (host).
+ *   wall_vel : n_walls x 3 wall velocities (host; may be NULL if n_walls = 0).
+ *   wall_ref : n_walls x 3 torque reference points (host; NULL = origin).
+ * Must be called before lbm_init_fields.  Errors: ARG (null map, id larger
+ * than n_walls, non-finite values), CAPACITY (n_walls > max_walls), STATE
+ * (after lbm_init_fields). */
+lbm_status lbm_set_walls(lbm_handle h, const uint8_t *wall_id, int32_t n_walls,
+                         const double *wall_vel, const double *wall_ref);
+
+/* Sphere kinematics for the next step (Sec. 2.3: the solid velocity at a
+ * boundary point is V + Omega x (x_b - X)).  Host arrays:
+ *   X, V, Omega : n x 3 (centre in [0, n_axis) per axis, velocity, angular
+ *                 velocity); R : n radii, 0 < R < min(nx,ny,nz)/2 - 1.
+ * The bodies given before step k are the geometry and velocities of step k;
+ * nodes that turn from solid to fluid are refilled with the equilibrium at
+ * rho0 and the velocity they had as solids.  The copy is asynchronous on the
+ * handle's stream (pinned staging).  Errors: ARG (null with n > 0, ranges,
+ * non-finite values), CAPACITY (n > max_bodies). */
+lbm_status lbm_set_bodies(lbm_handle h, int32_t n, const double *X, const double *V,
+                          const double *Omega, const double *R);
+
+/* Same from a device table d_table[n][10] = {X[3], V[3], Omega[3], R} in
+ * FP64, copied on the handle's stream.  The values are not checked on the
+ * host: a sphere with a radius outside (0, min(n)/2 - 1) or a centre outside
+ * the box is ignored by the rasteriser.  Errors: ARG, CAPACITY. */
+lbm_status lbm_set_bodies_device(lbm_handle h, int32_t n, const double *d_table);
+
+/* Initial state: f_i = f_i^eq(rho, u) at fluid nodes (no collision), the
+ * geometry of the current walls and bodies being both the initial geometry
+ * and that of step 1.  rho: N densities or NULL (rho0); u: 3N velocities,
+ * component-major (u[c*N + n]), or NULL (0).  Host arrays.  Resets the step
+ * counter and the forces.  Errors: ARG (non-positive or non-finite rho,
+ * non-finite u), HIP. */
+lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *u);
+
+/* Advance nsteps steps, asynchronously on the handle's stream.  Each step:
+ * re-rasterise the spheres if they were set since the previous step, then
+ * one fused kernel does pull streaming, interpolated bounce-back with the
+ * moving-boundary term, moments, Smagorinsky tau*, BGK + Guo collision and
+ * the per-body force/torque reduction.  Forces are those of the last step.
+ * With nan_guard_every = k the call synchronises every k steps and returns
+ * LBM_ERR_UNSTABLE if a fluid node had a non-finite or non-positive density
+ * or a non-finite velocity.  Errors: STATE (before lbm_init_fields), ARG
+ * (nsteps < 0), HIP, UNSTABLE. */
+lbm_status lbm_step(lbm_handle h, int32_t nsteps);
+
+/* Force and torque on every sphere then every wall, of the last step, in
+ * FP64 (host arrays of (n_bodies + n_walls) x 3).  Torques of spheres are
+ * about their centre, of walls about their reference point.  Synchronises
+ * the stream.  Errors: ARG, STATE, HIP. */
+lbm_status lbm_get_forces(lbm_handle h, double *F, double *T);
+
+/* Same into device memory, asynchronously: d_out[(n_bodies + n_walls) * 6]
+ * holds {Fx, Fy, Fz, Tx, Ty, Tz} per body.  Errors: ARG, STATE, HIP. */
+lbm_status lbm_get_forces_device(lbm_handle h, double *d_out);
+
+/* Post-collision populations of the current state as full f (not
+ * deviations), FP64, host array [19][N].  Solid nodes report the
+ * equilibrium at rho0 and their solid velocity.  Synchronises.
+ * Errors: ARG, STATE, HIP. */
+lbm_status lbm_get_populations(lbm_handle h, double *f);
+
+/* Overwrite the current state with full populations f [19][N] (host, FP64),
+ * converted to the storage type.  Errors: ARG (non-finite), STATE, HIP. */
+lbm_status lbm_set_populations(lbm_handle h, const double *f);
+
+/* Density rho[N] and velocity u[3N] (component-major) of the current state:
+ * rho = sum f, u = (sum f c - F/2)/rho, i.e. the velocity used by the last
+ * collision (which added F to the momentum).  Solid nodes report rho0 and
+ * their solid velocity.  Synchronises.  Errors: ARG, STATE, HIP. */
+lbm_status lbm_get_macro(lbm_handle h, double *rho, double *u);
+
+/* Owner map of the current state's geometry, int32 per node: -1 fluid,
+ * 0..n_walls-1 wall, n_walls + b sphere b.  Synchronises. */
+lbm_status lbm_get_owner(lbm_handle h, int32_t *owner);
+
+/* Checkpoint: with buf == NULL, *bytes receives the size needed; otherwise
+ * the populations (storage type), owner map, body and wall tables and
+ * counters are written to buf (host, *bytes >= size).  lbm_set_state
+ * restores a checkpoint of a handle with the same configuration; resuming
+ * reproduces the populations bit for bit.  Errors: ARG, STATE, HIP. */
+lbm_status lbm_get_state(lbm_handle h, void *buf, size_t *bytes);
+lbm_status lbm_set_state(lbm_handle h, const void *buf, size_t bytes);
+
+/* Sizes and counters of the handle (host-side values, no device work).
+ * Errors: ARG. */
+lbm_status lbm_get_info(lbm_handle h, lbm_info *info);
+
+/* Number of fluid nodes of the current state's geometry (a reduction over
+ * the owner map; synchronises).  Errors: ARG, HIP. */
+lbm_status lbm_count_fluid(lbm_handle h, int64_t *n_fluid);
+
+/* Timing of the fused step kernel with HIP events on the handle's stream:
+ * lbm_profile(h, 1) starts recording an event pair around every step-kernel
+ * launch (and clears earlier records), lbm_profile(h, 0) stops.
+ * lbm_profile_read synchronises and returns the summed kernel time in
+ * milliseconds and the number of launches recorded.  Errors: ARG, HIP. */
+lbm_status lbm_profile(lbm_handle h, int32_t enable);
+lbm_status lbm_profile_read(lbm_handle h, double *ms_total, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,368 @@
+"""Python binding of liblbm (the gfx950 D3Q19 moving-boundary LBM step).
+
+Argument marshalling only: every computation runs in the HIP library behind
+the C ABI declared in ``include/lbm.h``.  The module-level functions carry
+the C names (``lbm_create``, ``lbm_set_bodies``, ``lbm_step`` ...); host
+arrays are numpy arrays (converted to contiguous float64/uint8), device
+arrays are torch CUDA tensors or raw integer addresses, streams are
+``torch.cuda.Stream.cuda_stream`` handles or integers.
+
+Importing the package fails loudly if ``liblbm.so`` has not been built
+(``python __graft_entry__.py build``); there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+__all__ = [
+    "LBMError", "LBMConfig", "LBMInfo", "config", "Lattice",
+    "lbm_version", "lbm_create", "lbm_destroy", "lbm_last_error", "lbm_set_stream",
+    "lbm_set_walls", "lbm_set_bodies", "lbm_set_bodies_device", "lbm_init_fields",
+    "lbm_step", "lbm_get_forces", "lbm_get_forces_device", "lbm_get_populations",
+    "lbm_set_populations", "lbm_get_macro", "lbm_get_owner", "lbm_get_state",
+    "lbm_set_state", "lbm_get_info", "lbm_count_fluid", "lbm_profile", "lbm_profile_read",
+    "STORAGE", "BB_MODE", "LIB_PATH",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbm.so")
+
+STATUS = {0: "LBM_OK", 1: "LBM_ERR_ARG", 2: "LBM_ERR_OOM", 3: "LBM_ERR_HIP",
+          4: "LBM_ERR_STATE", 5: "LBM_ERR_UNSTABLE", 6: "LBM_ERR_CAPACITY"}
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+BB_MODE = {"bouzidi": 0, "halfway": 1}
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class LBMConfig(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("nz", ct.c_int32),
+                ("storage", ct.c_int32), ("tau0", ct.c_double), ("smag_c", ct.c_double),
+                ("rho0", ct.c_double), ("body_force", ct.c_double * 3),
+                ("bb_mode", ct.c_int32), ("max_bodies", ct.c_int32), ("max_walls", ct.c_int32),
+                ("nan_guard_every", ct.c_int32), ("stream", ct.c_void_p)]
+
+
+class LBMInfo(ct.Structure):
+    _fields_ = [("n_nodes", ct.c_int64), ("n_bodies", ct.c_int32),
+                ("n_walls", ct.c_int32), ("storage_bytes", ct.c_int32),
+                ("steps_done", ct.c_int32), ("device_bytes", ct.c_int64)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python __graft_entry__.py build` "
+                      "(there is no non-HIP fallback)")
+_L = ct.CDLL(LIB_PATH)
+
+_H = ct.c_void_p
+_dp = ct.POINTER(ct.c_double)
+_sig = {
+    "lbm_version": (ct.c_int32, []),
+    "lbm_create": (ct.c_int, [ct.POINTER(LBMConfig), ct.POINTER(_H)]),
+    "lbm_destroy": (None, [_H]),
+    "lbm_last_error": (ct.c_char_p, [_H]),
+    "lbm_set_stream": (ct.c_int, [_H, ct.c_void_p]),
+    "lbm_set_walls": (ct.c_int, [_H, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p]),
+    "lbm_set_bodies": (ct.c_int, [_H, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "lbm_set_bodies_device": (ct.c_int, [_H, ct.c_int32, ct.c_void_p]),
+    "lbm_init_fields": (ct.c_int, [_H, ct.c_void_p, ct.c_void_p]),
+    "lbm_step": (ct.c_int, [_H, ct.c_int32]),
+    "lbm_get_forces": (ct.c_int, [_H, ct.c_void_p, ct.c_void_p]),
+    "lbm_get_forces_device": (ct.c_int, [_H, ct.c_void_p]),
+    "lbm_get_populations": (ct.c_int, [_H, ct.c_void_p]),
+    "lbm_set_populations": (ct.c_int, [_H, ct.c_void_p]),
+    "lbm_get_macro": (ct.c_int, [_H, ct.c_void_p, ct.c_void_p]),
+    "lbm_get_owner": (ct.c_int, [_H, ct.c_void_p]),
+    "lbm_get_state": (ct.c_int, [_H, ct.c_void_p, ct.POINTER(ct.c_size_t)]),
+    "lbm_set_state": (ct.c_int, [_H, ct.c_void_p, ct.c_size_t]),
+    "lbm_get_info": (ct.c_int, [_H, ct.POINTER(LBMInfo)]),
+    "lbm_count_fluid": (ct.c_int, [_H, ct.POINTER(ct.c_int64)]),
+    "lbm_profile": (ct.c_int, [_H, ct.c_int32]),
+    "lbm_profile_read": (ct.c_int, [_H, _dp, ct.POINTER(ct.c_int64)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(_L, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+def _check(h, st):
+    if st != 0:
+        msg = _L.lbm_last_error(h)
+        raise LBMError(st, msg.decode() if msg else "")
+
+
+def _host(a, dtype, n=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=dtype))
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return ct.c_void_p(t)
+    return ct.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return ct.c_void_p(stream)
+    return ct.c_void_p(stream.cuda_stream)
+
+
+# ---- C functions, same names -------------------------------------------------
+
+def lbm_version() -> int:
+    return _L.lbm_version()
+
+
+def config(nx, ny, nz, tau0, smag_c, rho0=1.0, body_force=(0.0, 0.0, 0.0), storage="f32",
+           bb_mode="bouzidi", max_bodies=0, max_walls=0, nan_guard_every=0, stream=None) -> LBMConfig:
+    c = LBMConfig()
+    c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
+    c.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    c.tau0, c.smag_c, c.rho0 = float(tau0), float(smag_c), float(rho0)
+    c.body_force[:] = [float(v) for v in body_force]
+    c.bb_mode = BB_MODE[bb_mode] if isinstance(bb_mode, str) else int(bb_mode)
+    c.max_bodies, c.max_walls = int(max_bodies), int(max_walls)
+    c.nan_guard_every = int(nan_guard_every)
+    c.stream = _stream_ptr(stream)
+    return c
+
+
+def lbm_create(cfg: LBMConfig) -> int:
+    h = _H()
+    st = _L.lbm_create(ct.byref(cfg), ct.byref(h))
+    if st != 0:
+        raise LBMError(st, "lbm_create rejected the configuration or could not allocate")
+    return h.value
+
+
+def lbm_destroy(h) -> None:
+    _L.lbm_destroy(h)
+
+
+def lbm_last_error(h) -> str:
+    r = _L.lbm_last_error(h)
+    return r.decode() if r else ""
+
+
+def lbm_set_stream(h, stream) -> None:
+    _check(h, _L.lbm_set_stream(h, _stream_ptr(stream)))
+
+
+def lbm_set_walls(h, wall_id, wall_vel, wall_ref=None) -> None:
+    w = _host(wall_id, np.uint8)
+    v = _host(wall_vel, np.float64).reshape(-1, 3) if wall_vel is not None else np.zeros((0, 3))
+    r = _host(wall_ref, np.float64).reshape(-1, 3) if wall_ref is not None else None
+    _check(h, _L.lbm_set_walls(h, _ptr(w), len(v), _ptr(v) if len(v) else None, _ptr(r)))
+
+
+def lbm_set_bodies(h, X, V, Omega, R) -> None:
+    R = _host(R, np.float64).reshape(-1)
+    n = len(R)
+    X, V, Om = (_host(a, np.float64, 3 * n) for a in (X, V, Omega))
+    _check(h, _L.lbm_set_bodies(h, n, _ptr(X), _ptr(V), _ptr(Om), _ptr(R)))
+
+
+def lbm_set_bodies_device(h, n, d_table) -> None:
+    _check(h, _L.lbm_set_bodies_device(h, int(n), _dev_ptr(d_table)))
+
+
+def lbm_init_fields(h, rho=None, u=None) -> None:
+    r = _host(rho, np.float64) if rho is not None else None
+    v = _host(u, np.float64) if u is not None else None
+    _check(h, _L.lbm_init_fields(h, _ptr(r), _ptr(v)))
+
+
+def lbm_step(h, nsteps=1) -> None:
+    _check(h, _L.lbm_step(h, int(nsteps)))
+
+
+def lbm_get_info(h) -> dict:
+    info = LBMInfo()
+    _check(h, _L.lbm_get_info(h, ct.byref(info)))
+    return {k: getattr(info, k) for k, _ in LBMInfo._fields_}
+
+
+def lbm_count_fluid(h) -> int:
+    n = ct.c_int64(0)
+    _check(h, _L.lbm_count_fluid(h, ct.byref(n)))
+    return n.value
+
+
+def lbm_get_forces(h, nbt=None):
+    if nbt is None:
+        i = lbm_get_info(h)
+        nbt = i["n_bodies"] + i["n_walls"]
+    F = np.zeros((nbt, 3))
+    T = np.zeros((nbt, 3))
+    _check(h, _L.lbm_get_forces(h, _ptr(F), _ptr(T)))
+    return F, T
+
+
+def lbm_get_forces_device(h, d_out) -> None:
+    _check(h, _L.lbm_get_forces_device(h, _dev_ptr(d_out)))
+
+
+def lbm_get_populations(h, shape):
+    nz, ny, nx = shape
+    f = np.zeros((19, nz, ny, nx))
+    _check(h, _L.lbm_get_populations(h, _ptr(f)))
+    return f
+
+
+def lbm_set_populations(h, f) -> None:
+    f = _host(f, np.float64)
+    _check(h, _L.lbm_set_populations(h, _ptr(f)))
+
+
+def lbm_get_macro(h, shape):
+    nz, ny, nx = shape
+    rho = np.zeros((nz, ny, nx))
+    u = np.zeros((3, nz, ny, nx))
+    _check(h, _L.lbm_get_macro(h, _ptr(rho), _ptr(u)))
+    return rho, u
+
+
+def lbm_get_owner(h, shape):
+    own = np.zeros(shape, np.int32)
+    _check(h, _L.lbm_get_owner(h, _ptr(own)))
+    return own
+
+
+def lbm_get_state(h) -> bytes:
+    n = ct.c_size_t(0)
+    _check(h, _L.lbm_get_state(h, None, ct.byref(n)))
+    buf = ct.create_string_buffer(n.value)
+    _check(h, _L.lbm_get_state(h, buf, ct.byref(n)))
+    return buf.raw[:n.value]
+
+
+def lbm_set_state(h, state: bytes) -> None:
+    _check(h, _L.lbm_set_state(h, state, len(state)))
+
+
+def lbm_profile(h, enable) -> None:
+    _check(h, _L.lbm_profile(h, int(bool(enable))))
+
+
+def lbm_profile_read(h):
+    ms = ct.c_double(0.0)
+    n = ct.c_int64(0)
+    _check(h, _L.lbm_profile_read(h, ct.byref(ms), ct.byref(n)))
+    return ms.value, n.value
+
+
+# ---- convenience object over one handle -----------------------------------------
+
+class Lattice:
+    """One handle with the calls above as methods (shapes remembered)."""
+
+    def __init__(self, cfg: LBMConfig):
+        self.cfg = cfg
+        self.shape = (cfg.nz, cfg.ny, cfg.nx)
+        self.h = lbm_create(cfg)
+        self._nbt = 0
+        self._n_walls = 0
+        self._nb = 0
+
+    @classmethod
+    def from_case(cls, case, storage="f32", bb_mode="bouzidi", stream=None, max_bodies=None,
+                  nan_guard_every=0, init=True):
+        nw = case.n_walls
+        cfg = config(case.nx, case.ny, case.nz, case.tau0, case.smag_c, case.rho0, case.body_force,
+                     storage=storage, bb_mode=bb_mode,
+                     max_bodies=case.n_bodies if max_bodies is None else max_bodies,
+                     max_walls=nw, nan_guard_every=nan_guard_every, stream=stream)
+        lat = cls(cfg)
+        if case.wall_id is not None:
+            lat.set_walls(case.wall_id, case.wall_vel, case.wall_ref)
+        lat.set_bodies(*case.bodies_at(0))
+        if init:
+            lat.init_fields(case.rho_init, case.u_init)
+        return lat
+
+    def close(self):
+        if self.h:
+            lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        lbm_set_stream(self.h, stream)
+
+    def set_walls(self, wall_id, wall_vel, wall_ref=None):
+        lbm_set_walls(self.h, wall_id, wall_vel, wall_ref)
+        self._n_walls = 0 if wall_vel is None else len(np.asarray(wall_vel).reshape(-1, 3))
+
+    def set_bodies(self, X, V, Omega, R):
+        lbm_set_bodies(self.h, X, V, Omega, R)
+        self._nb_next = len(np.asarray(R).reshape(-1))
+
+    def set_bodies_device(self, n, d_table):
+        lbm_set_bodies_device(self.h, n, d_table)
+
+    def init_fields(self, rho=None, u=None):
+        lbm_init_fields(self.h, rho, u)
+
+    def step(self, nsteps=1):
+        lbm_step(self.h, nsteps)
+
+    def get_forces(self):
+        return lbm_get_forces(self.h)
+
+    def get_forces_device(self, d_out):
+        lbm_get_forces_device(self.h, d_out)
+
+    def get_populations(self):
+        return lbm_get_populations(self.h, self.shape)
+
+    def set_populations(self, f):
+        lbm_set_populations(self.h, f)
+
+    def get_macro(self):
+        return lbm_get_macro(self.h, self.shape)
+
+    def get_owner(self):
+        return lbm_get_owner(self.h, self.shape)
+
+    def get_state(self):
+        return lbm_get_state(self.h)
+
+    def set_state(self, s):
+        lbm_set_state(self.h, s)
+
+    def info(self):
+        return lbm_get_info(self.h)
+
+    def count_fluid(self):
+        return lbm_count_fluid(self.h)
+
+    def profile(self, enable):
+        lbm_profile(self.h, enable)
+
+    def profile_read(self):
+        return lbm_profile_read(self.h)

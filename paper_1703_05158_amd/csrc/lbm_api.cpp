@@ -1,0 +1,662 @@
+// Host side of liblbm: argument validation, device memory, state machine and
+// the per-step launch sequence.  Every entry point returns an lbm_status and
+// never throws across the C ABI.
+#include "lbm.h"
+#include "lbm_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+using namespace lbm;
+
+struct lbm_ctx {
+    lbm_config cfg{};
+    hipStream_t stream = nullptr;
+    int N = 0;
+    int sbytes = 4;
+    void *pop[2] = {nullptr, nullptr};
+    int cur = 0;                       // pop[cur] holds the current (post-collision) state
+    uint16_t *own = nullptr;
+    uint8_t *wall_map = nullptr;
+    double *tab[2] = {nullptr, nullptr};
+    int ts = 0;                        // tab[ts]: bodies of the current state's geometry
+    int nb_state = 0, nb_next = 0;
+    bool dirty = false;                // tab[1-ts] set since the last step / init
+    double *walls = nullptr;
+    int n_walls = 0;
+    double *acc = nullptr;             // (max_bodies + max_walls) * 6
+    int *flag = nullptr;
+    int *flag_host = nullptr;
+    double *scratch = nullptr;         // 4N doubles, export/import staging (lazy)
+    double *pinned = nullptr;          // max_bodies * 10 doubles, set_bodies staging
+    hipEvent_t stage_evt = nullptr;
+    bool initialized = false;
+    int steps_done = 0;
+    int64_t device_bytes = 0;
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+    std::string err;
+};
+
+namespace {
+
+const char *kNullHandle = "null lbm_handle";
+
+lbm_status fail(lbm_ctx *h, lbm_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    return st;
+}
+
+#define HIP_TRY(h, expr)                                                                         \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((h), e_ == hipErrorOutOfMemory ? LBM_ERR_OOM : LBM_ERR_HIP, "%s: %s (%s)", \
+                        #expr, hipGetErrorString(e_), hipGetErrorName(e_));                      \
+    } while (0)
+
+bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+template <typename T>
+hipError_t dalloc(lbm_ctx *h, T **p, size_t bytes)
+{
+    hipError_t e = hipMalloc((void **)p, bytes ? bytes : 16);
+    if (e == hipSuccess) h->device_bytes += (int64_t)bytes;
+    return e;
+}
+
+GeomArgs geom(const lbm_ctx *h)
+{
+    GeomArgs g{};
+    g.nx = h->cfg.nx;
+    g.ny = h->cfg.ny;
+    g.nz = h->cfg.nz;
+    g.N = h->N;
+    g.n_walls = h->n_walls;
+    g.bodies = h->tab[h->ts];
+    g.nb = h->nb_state;
+    g.bodies2 = h->tab[1 - h->ts];
+    g.nb2 = 0;
+    g.own = h->own;
+    g.pop = h->pop[h->cur];
+    g.rho0 = (float)h->cfg.rho0;
+    return g;
+}
+
+// Rebuild the whole owner map: walls, spheres of tab[ts], near flags.
+lbm_status rasterize_full(lbm_ctx *h)
+{
+    GeomArgs g = geom(h);
+    HIP_TRY(h, launch_walls_init(h->wall_map, h->own, h->N, h->stream));
+    HIP_TRY(h, launch_stamp(g, h->stream));
+    HIP_TRY(h, launch_flags_full(g, h->stream));
+    return LBM_OK;
+}
+
+// Move from the geometry of tab[ts] to that of tab[1-ts] (bodies set since
+// the last step), refilling uncovered nodes in the current population buffer.
+lbm_status rasterize_update(lbm_ctx *h)
+{
+    GeomArgs old_g = geom(h);
+    GeomArgs new_g = old_g;
+    new_g.bodies = h->tab[1 - h->ts];
+    new_g.nb = h->nb_next;
+    HIP_TRY(h, launch_vacate(old_g, h->stream));
+    HIP_TRY(h, launch_stamp(new_g, h->stream));
+    HIP_TRY(h, launch_refill(h->cfg.storage, old_g, h->stream));
+    GeomArgs fl = old_g;
+    fl.bodies2 = new_g.bodies;
+    fl.nb2 = new_g.nb;
+    HIP_TRY(h, launch_flags_bodies(fl, h->stream));
+    h->ts = 1 - h->ts;
+    h->nb_state = h->nb_next;
+    h->dirty = false;
+    return LBM_OK;
+}
+
+lbm_status check_ready(lbm_ctx *h)
+{
+    if (!h->initialized) return fail(h, LBM_ERR_STATE, "lbm_init_fields has not been called");
+    return LBM_OK;
+}
+
+lbm_status ensure_scratch(lbm_ctx *h)
+{
+    if (!h->scratch) HIP_TRY(h, dalloc(h, &h->scratch, sizeof(double) * (size_t)h->N * 4));
+    return LBM_OK;
+}
+
+// Copy on the handle's stream and wait for it.
+lbm_status copy_sync(lbm_ctx *h, void *dst, const void *src, size_t bytes, hipMemcpyKind kind)
+{
+    if (bytes == 0) return LBM_OK;
+    HIP_TRY(h, hipMemcpyAsync(dst, src, bytes, kind, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+#define TRY(expr)                        \
+    do {                                 \
+        lbm_status st_ = (expr);         \
+        if (st_ != LBM_OK) return st_;   \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int32_t lbm_version(void) { return 10000; }
+
+const char *lbm_last_error(lbm_handle h) { return h ? h->err.c_str() : kNullHandle; }
+
+lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
+{
+    if (!cfg || !out) return LBM_ERR_ARG;
+    const lbm_config &c = *cfg;
+    if (c.nx < 1 || c.ny < 1 || c.nz < 1) return LBM_ERR_ARG;
+    const long long N = (long long)c.nx * c.ny * c.nz;
+    if (N > (long long)0x7fffffff / 2) return LBM_ERR_ARG;
+    if (!(c.tau0 > 0.5) || !std::isfinite(c.tau0)) return LBM_ERR_ARG;
+    if (!(c.smag_c >= 0.0) || !std::isfinite(c.smag_c)) return LBM_ERR_ARG;
+    if (!(c.rho0 > 0.0) || !std::isfinite(c.rho0)) return LBM_ERR_ARG;
+    if (!finite_all(c.body_force, 3)) return LBM_ERR_ARG;
+    if (c.storage < 0 || c.storage > 2) return LBM_ERR_ARG;
+    if (c.bb_mode < 0 || c.bb_mode > 1) return LBM_ERR_ARG;
+    if (c.max_bodies < 0 || c.max_walls < 0 || c.max_walls > 255) return LBM_ERR_ARG;
+    if ((long long)c.max_bodies + c.max_walls > kMaxIds) return LBM_ERR_ARG;
+    if (c.nan_guard_every < 0) return LBM_ERR_ARG;
+
+    lbm_ctx *h = new (std::nothrow) lbm_ctx();
+    if (!h) return LBM_ERR_OOM;
+    h->cfg = c;
+    h->stream = (hipStream_t)c.stream;
+    h->N = (int)N;
+    h->sbytes = c.storage == 0 ? 4 : 2;
+    auto bail = [&](lbm_status st) {
+        lbm_destroy(h);
+        return st;
+    };
+    const size_t popb = (size_t)kQ * N * h->sbytes;
+    const int nbt = c.max_bodies + c.max_walls;
+    if (dalloc(h, &h->pop[0], popb) != hipSuccess || dalloc(h, &h->pop[1], popb) != hipSuccess ||
+        dalloc(h, &h->own, sizeof(uint16_t) * N + 4) != hipSuccess ||
+        dalloc(h, &h->wall_map, (size_t)N) != hipSuccess ||
+        dalloc(h, &h->tab[0], sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
+        dalloc(h, &h->tab[1], sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
+        dalloc(h, &h->walls, sizeof(double) * kWallStride * std::max(c.max_walls, 1)) != hipSuccess ||
+        dalloc(h, &h->acc, sizeof(double) * 6 * std::max(nbt, 1)) != hipSuccess ||
+        dalloc(h, &h->flag, sizeof(int)) != hipSuccess)
+        return bail(LBM_ERR_OOM);
+    if (hipHostMalloc((void **)&h->pinned, sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
+        hipHostMalloc((void **)&h->flag_host, sizeof(int)) != hipSuccess)
+        return bail(LBM_ERR_OOM);
+    if (hipEventCreateWithFlags(&h->stage_evt, hipEventDisableTiming) != hipSuccess) return bail(LBM_ERR_HIP);
+    if (hipMemsetAsync(h->wall_map, 0, (size_t)N, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->pop[0], 0, popb, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->pop[1], 0, popb, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->acc, 0, sizeof(double) * 6 * std::max(nbt, 1), h->stream) != hipSuccess ||
+        hipMemsetAsync(h->flag, 0, sizeof(int), h->stream) != hipSuccess)
+        return bail(LBM_ERR_HIP);
+    if (rasterize_full(h) != LBM_OK) return bail(LBM_ERR_HIP);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(LBM_ERR_HIP);
+    *out = h;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_handle h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    for (auto &p : h->prof_ev) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    void *dev[] = {h->pop[0], h->pop[1], h->own, h->wall_map, h->tab[0], h->tab[1],
+                   h->walls, h->acc, h->flag, h->scratch};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    if (h->flag_host) (void)hipHostFree(h->flag_host);
+    if (h->stage_evt) (void)hipEventDestroy(h->stage_evt);
+    delete h;
+}
+
+lbm_status lbm_set_stream(lbm_handle h, void *stream)
+{
+    if (!h) return LBM_ERR_ARG;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->stream = (hipStream_t)stream;
+    h->cfg.stream = stream;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_walls(lbm_handle h, const uint8_t *wall_id, int32_t n_walls, const double *wall_vel,
+                         const double *wall_ref)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (h->initialized) return fail(h, LBM_ERR_STATE, "walls must be set before lbm_init_fields");
+    if (!wall_id) return fail(h, LBM_ERR_ARG, "wall_id is NULL");
+    if (n_walls < 0) return fail(h, LBM_ERR_ARG, "n_walls < 0");
+    if (n_walls > h->cfg.max_walls) return fail(h, LBM_ERR_CAPACITY, "n_walls %d > max_walls %d", n_walls, h->cfg.max_walls);
+    if (n_walls > 0 && !wall_vel) return fail(h, LBM_ERR_ARG, "wall_vel is NULL");
+    if (n_walls > 0 && !finite_all(wall_vel, 3 * (size_t)n_walls)) return fail(h, LBM_ERR_ARG, "non-finite wall velocity");
+    if (wall_ref && n_walls > 0 && !finite_all(wall_ref, 3 * (size_t)n_walls))
+        return fail(h, LBM_ERR_ARG, "non-finite wall reference");
+    for (int n = 0; n < h->N; ++n)
+        if (wall_id[n] > n_walls) return fail(h, LBM_ERR_ARG, "wall id %d at node %d exceeds n_walls", wall_id[n], n);
+    std::vector<double> wt((size_t)kWallStride * std::max(n_walls, 1), 0.0);
+    for (int w = 0; w < n_walls; ++w)
+        for (int a = 0; a < 3; ++a) {
+            wt[w * kWallStride + a] = wall_vel[3 * w + a];
+            wt[w * kWallStride + 3 + a] = wall_ref ? wall_ref[3 * w + a] : 0.0;
+        }
+    TRY(copy_sync(h, h->wall_map, wall_id, (size_t)h->N, hipMemcpyHostToDevice));
+    TRY(copy_sync(h, h->walls, wt.data(), sizeof(double) * wt.size(), hipMemcpyHostToDevice));
+    h->n_walls = n_walls;
+    return rasterize_full(h);
+}
+
+static lbm_status stage_bodies(lbm_ctx *h, int32_t n)
+{
+    HIP_TRY(h, hipMemcpyAsync(h->tab[1 - h->ts], h->pinned, sizeof(double) * kBodyStride * (size_t)n,
+                              hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipEventRecord(h->stage_evt, h->stream));
+    h->nb_next = n;
+    h->dirty = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_bodies(lbm_handle h, int32_t n, const double *X, const double *V, const double *Omega,
+                          const double *R)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (n < 0) return fail(h, LBM_ERR_ARG, "n < 0");
+    if (n > h->cfg.max_bodies) return fail(h, LBM_ERR_CAPACITY, "n %d > max_bodies %d", n, h->cfg.max_bodies);
+    if (n > 0 && (!X || !V || !Omega || !R)) return fail(h, LBM_ERR_ARG, "NULL body array");
+    const double dims[3] = {(double)h->cfg.nx, (double)h->cfg.ny, (double)h->cfg.nz};
+    const double rmax = 0.5 * std::min(dims[0], std::min(dims[1], dims[2])) - 1.0;
+    for (int b = 0; b < n; ++b) {
+        for (int a = 0; a < 3; ++a) {
+            if (!(X[3 * b + a] >= 0.0 && X[3 * b + a] < dims[a]))
+                return fail(h, LBM_ERR_ARG, "sphere %d centre outside [0, n) on axis %d", b, a);
+            if (!std::isfinite(V[3 * b + a]) || !std::isfinite(Omega[3 * b + a]))
+                return fail(h, LBM_ERR_ARG, "sphere %d has a non-finite velocity", b);
+        }
+        if (!(R[b] > 0.0 && R[b] < rmax))
+            return fail(h, LBM_ERR_ARG, "sphere %d radius %g outside (0, %g)", b, R[b], rmax);
+    }
+    HIP_TRY(h, hipEventSynchronize(h->stage_evt));  // staging buffer free again
+    for (int b = 0; b < n; ++b) {
+        double *t = h->pinned + (size_t)b * kBodyStride;
+        for (int a = 0; a < 3; ++a) {
+            t[a] = X[3 * b + a];
+            t[3 + a] = V[3 * b + a];
+            t[6 + a] = Omega[3 * b + a];
+        }
+        t[9] = R[b];
+    }
+    return stage_bodies(h, n);
+}
+
+lbm_status lbm_set_bodies_device(lbm_handle h, int32_t n, const double *d_table)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (n < 0) return fail(h, LBM_ERR_ARG, "n < 0");
+    if (n > h->cfg.max_bodies) return fail(h, LBM_ERR_CAPACITY, "n %d > max_bodies %d", n, h->cfg.max_bodies);
+    if (n > 0 && !d_table) return fail(h, LBM_ERR_ARG, "d_table is NULL");
+    if (n > 0)
+        HIP_TRY(h, hipMemcpyAsync(h->tab[1 - h->ts], d_table, sizeof(double) * kBodyStride * (size_t)n,
+                                  hipMemcpyDeviceToDevice, h->stream));
+    h->nb_next = n;
+    h->dirty = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *u)
+{
+    if (!h) return LBM_ERR_ARG;
+    const size_t N = (size_t)h->N;
+    if (rho)
+        for (size_t n = 0; n < N; ++n)
+            if (!(rho[n] > 0.0) || !std::isfinite(rho[n])) return fail(h, LBM_ERR_ARG, "rho[%zu] not positive and finite", n);
+    if (u && !finite_all(u, 3 * N)) return fail(h, LBM_ERR_ARG, "non-finite initial velocity");
+    if (h->dirty) {
+        h->ts = 1 - h->ts;
+        h->nb_state = h->nb_next;
+        h->dirty = false;
+    }
+    TRY(rasterize_full(h));
+    const double *rho_dev = nullptr, *u_dev = nullptr;
+    if (rho || u) TRY(ensure_scratch(h));
+    if (rho) {
+        TRY(copy_sync(h, h->scratch, rho, sizeof(double) * N, hipMemcpyHostToDevice));
+        rho_dev = h->scratch;
+    }
+    if (u) {
+        TRY(copy_sync(h, h->scratch + N, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice));
+        u_dev = h->scratch + N;
+    }
+    GeomArgs g = geom(h);
+    HIP_TRY(h, launch_init_pop(h->cfg.storage, g, rho_dev, u_dev, h->stream));
+    HIP_TRY(h, launch_zero(h->acc, 6 * (h->cfg.max_bodies + h->cfg.max_walls), h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->initialized = true;
+    h->steps_done = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_handle h, int32_t nsteps)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (nsteps < 0) return fail(h, LBM_ERR_ARG, "nsteps < 0");
+    lbm_status st = check_ready(h);
+    if (st != LBM_OK) return st;
+    const lbm_config &c = h->cfg;
+    StepArgs a{};
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.nz = c.nz;
+    a.N = h->N;
+    a.div_nx = make_fastdiv((uint32_t)c.nx);
+    a.div_ny = make_fastdiv((uint32_t)c.ny);
+    a.tau0 = (float)c.tau0;
+    a.smag_k = (float)(18.0 * std::sqrt(2.0) * c.smag_c * c.smag_c);
+    a.rho0 = (float)c.rho0;
+    a.fx = (float)c.body_force[0];
+    a.fy = (float)c.body_force[1];
+    a.fz = (float)c.body_force[2];
+    a.halfway = c.bb_mode == LBM_BB_HALFWAY;
+    a.nblocks = (h->N + kBlock - 1) / kBlock;
+    a.own = h->own;
+    a.walls = h->walls;
+    a.acc = h->acc;
+    a.flag = c.nan_guard_every > 0 ? h->flag : nullptr;
+    for (int s = 0; s < nsteps; ++s) {
+        if (h->dirty && (st = rasterize_update(h)) != LBM_OK) return st;
+        a.n_walls = h->n_walls;
+        a.nb = h->nb_state;
+        a.bodies = h->tab[h->ts];
+        a.src = h->pop[h->cur];
+        a.dst = h->pop[1 - h->cur];
+        HIP_TRY(h, launch_zero(h->acc, 6 * (a.nb + a.n_walls), h->stream));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (h->prof) {
+            HIP_TRY(h, hipEventCreate(&e0));
+            HIP_TRY(h, hipEventCreate(&e1));
+            HIP_TRY(h, hipEventRecord(e0, h->stream));
+        }
+        HIP_TRY(h, launch_step(c.storage, a, h->stream));
+        if (h->prof) {
+            HIP_TRY(h, hipEventRecord(e1, h->stream));
+            h->prof_ev.emplace_back(e0, e1);
+        }
+        h->cur = 1 - h->cur;
+        h->steps_done++;
+        if (c.nan_guard_every > 0 && (h->steps_done % c.nan_guard_every == 0 || s == nsteps - 1)) {
+            HIP_TRY(h, hipMemcpyAsync(h->flag_host, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            if (*h->flag_host)
+                return fail(h, LBM_ERR_UNSTABLE, "non-finite or non-positive density/velocity by step %d",
+                            h->steps_done);
+        }
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_get_forces(lbm_handle h, double *F, double *T)
+{
+    if (!h) return LBM_ERR_ARG;
+    lbm_status st = check_ready(h);
+    if (st != LBM_OK) return st;
+    const int nbt = h->nb_state + h->n_walls;
+    if (nbt > 0 && (!F || !T)) return fail(h, LBM_ERR_ARG, "NULL output");
+    std::vector<double> buf((size_t)6 * std::max(nbt, 1));
+    HIP_TRY(h, hipMemcpyAsync(buf.data(), h->acc, sizeof(double) * 6 * nbt, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (int b = 0; b < nbt; ++b)
+        for (int a = 0; a < 3; ++a) {
+            F[3 * b + a] = buf[6 * b + a];
+            T[3 * b + a] = buf[6 * b + 3 + a];
+        }
+    return LBM_OK;
+}
+
+lbm_status lbm_get_forces_device(lbm_handle h, double *d_out)
+{
+    if (!h) return LBM_ERR_ARG;
+    lbm_status st = check_ready(h);
+    if (st != LBM_OK) return st;
+    const int nbt = h->nb_state + h->n_walls;
+    if (nbt > 0 && !d_out) return fail(h, LBM_ERR_ARG, "NULL output");
+    if (nbt > 0)
+        HIP_TRY(h, hipMemcpyAsync(d_out, h->acc, sizeof(double) * 6 * nbt, hipMemcpyDeviceToDevice, h->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_handle h, double *f)
+{
+    if (!h || !f) return h ? fail(h, LBM_ERR_ARG, "NULL output") : LBM_ERR_ARG;
+    lbm_status st = check_ready(h);
+    if (st != LBM_OK) return st;
+    if ((st = ensure_scratch(h)) != LBM_OK) return st;
+    GeomArgs g = geom(h);
+    for (int i = 0; i < kQ; ++i) {
+        HIP_TRY(h, launch_export_pop(h->cfg.storage, g, h->walls, i, h->scratch, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(f + (size_t)i * h->N, h->scratch, sizeof(double) * h->N, hipMemcpyDeviceToHost,
+                                  h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_handle h, const double *f)
+{
+    if (!h || !f) return h ? fail(h, LBM_ERR_ARG, "NULL input") : LBM_ERR_ARG;
+    lbm_status st = check_ready(h);
+    if (st != LBM_OK) return st;
+    if (!finite_all(f, (size_t)kQ * h->N)) return fail(h, LBM_ERR_ARG, "non-finite populations");
+    if ((st = ensure_scratch(h)) != LBM_OK) return st;
+    for (int i = 0; i < kQ; ++i) {
+        TRY(copy_sync(h, h->scratch, f + (size_t)i * h->N, sizeof(double) * h->N, hipMemcpyHostToDevice));
+        HIP_TRY(h, launch_import_pop(h->cfg.storage, h->N, i, (float)h->cfg.rho0, h->scratch, h->pop[h->cur],
+                                     h->stream));
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_get_macro(lbm_handle h, double *rho, double *u)
+{
+    if (!h || !rho || !u) return h ? fail(h, LBM_ERR_ARG, "NULL output") : LBM_ERR_ARG;
+    TRY(check_ready(h));
+    TRY(ensure_scratch(h));
+    const size_t N = (size_t)h->N;
+    GeomArgs g = geom(h);
+    HIP_TRY(h, launch_export_macro(h->cfg.storage, g, h->walls, h->cfg.body_force[0], h->cfg.body_force[1],
+                                   h->cfg.body_force[2], h->scratch, h->scratch + N, h->stream));
+    TRY(copy_sync(h, rho, h->scratch, sizeof(double) * N, hipMemcpyDeviceToHost));
+    TRY(copy_sync(h, u, h->scratch + N, sizeof(double) * 3 * N, hipMemcpyDeviceToHost));
+    return LBM_OK;
+}
+
+lbm_status lbm_get_owner(lbm_handle h, int32_t *owner)
+{
+    if (!h || !owner) return h ? fail(h, LBM_ERR_ARG, "NULL output") : LBM_ERR_ARG;
+    lbm_status st = ensure_scratch(h);
+    if (st != LBM_OK) return st;
+    int32_t *d = reinterpret_cast<int32_t *>(h->scratch);
+    HIP_TRY(h, launch_export_owner(h->own, h->N, d, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(owner, d, sizeof(int32_t) * h->N, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+namespace {
+struct StateHeader {
+    char magic[8];
+    int32_t version, nx, ny, nz, storage, n_walls, nb_state, nb_next, dirty, steps_done, max_bodies, max_walls;
+};
+}  // namespace
+
+lbm_status lbm_get_state(lbm_handle h, void *buf, size_t *bytes)
+{
+    if (!h || !bytes) return h ? fail(h, LBM_ERR_ARG, "NULL size") : LBM_ERR_ARG;
+    lbm_status st = check_ready(h);
+    if (st != LBM_OK) return st;
+    const size_t popb = (size_t)kQ * h->N * h->sbytes;
+    const size_t tabb = sizeof(double) * kBodyStride * std::max(h->cfg.max_bodies, 1);
+    const size_t wallb = sizeof(double) * kWallStride * std::max(h->cfg.max_walls, 1);
+    const size_t accb = sizeof(double) * 6 * std::max(h->cfg.max_bodies + h->cfg.max_walls, 1);
+    const size_t need = sizeof(StateHeader) + popb + sizeof(uint16_t) * h->N + (size_t)h->N + 2 * tabb + wallb + accb;
+    if (!buf) {
+        *bytes = need;
+        return LBM_OK;
+    }
+    if (*bytes < need) return fail(h, LBM_ERR_ARG, "buffer of %zu bytes < %zu needed", *bytes, need);
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    StateHeader hd{};
+    memcpy(hd.magic, "LBMSTAT1", 8);
+    hd.version = lbm_version();
+    hd.nx = h->cfg.nx;
+    hd.ny = h->cfg.ny;
+    hd.nz = h->cfg.nz;
+    hd.storage = h->cfg.storage;
+    hd.n_walls = h->n_walls;
+    hd.nb_state = h->nb_state;
+    hd.nb_next = h->nb_next;
+    hd.dirty = h->dirty;
+    hd.steps_done = h->steps_done;
+    hd.max_bodies = h->cfg.max_bodies;
+    hd.max_walls = h->cfg.max_walls;
+    char *p = static_cast<char *>(buf);
+    memcpy(p, &hd, sizeof hd);
+    p += sizeof hd;
+    TRY(copy_sync(h, p, h->pop[h->cur], popb, hipMemcpyDeviceToHost));
+    p += popb;
+    TRY(copy_sync(h, p, h->own, sizeof(uint16_t) * h->N, hipMemcpyDeviceToHost));
+    p += sizeof(uint16_t) * h->N;
+    TRY(copy_sync(h, p, h->wall_map, (size_t)h->N, hipMemcpyDeviceToHost));
+    p += h->N;
+    TRY(copy_sync(h, p, h->tab[h->ts], tabb, hipMemcpyDeviceToHost));
+    p += tabb;
+    TRY(copy_sync(h, p, h->tab[1 - h->ts], tabb, hipMemcpyDeviceToHost));
+    p += tabb;
+    TRY(copy_sync(h, p, h->walls, wallb, hipMemcpyDeviceToHost));
+    p += wallb;
+    TRY(copy_sync(h, p, h->acc, accb, hipMemcpyDeviceToHost));
+    *bytes = need;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_handle h, const void *buf, size_t bytes)
+{
+    if (!h || !buf) return h ? fail(h, LBM_ERR_ARG, "NULL buffer") : LBM_ERR_ARG;
+    const size_t popb = (size_t)kQ * h->N * h->sbytes;
+    const size_t tabb = sizeof(double) * kBodyStride * std::max(h->cfg.max_bodies, 1);
+    const size_t wallb = sizeof(double) * kWallStride * std::max(h->cfg.max_walls, 1);
+    const size_t accb = sizeof(double) * 6 * std::max(h->cfg.max_bodies + h->cfg.max_walls, 1);
+    const size_t need = sizeof(StateHeader) + popb + sizeof(uint16_t) * h->N + (size_t)h->N + 2 * tabb + wallb + accb;
+    if (bytes < need) return fail(h, LBM_ERR_ARG, "state of %zu bytes < %zu expected", bytes, need);
+    StateHeader hd;
+    memcpy(&hd, buf, sizeof hd);
+    if (memcmp(hd.magic, "LBMSTAT1", 8) != 0 || hd.nx != h->cfg.nx || hd.ny != h->cfg.ny || hd.nz != h->cfg.nz ||
+        hd.storage != h->cfg.storage || hd.max_bodies != h->cfg.max_bodies || hd.max_walls != h->cfg.max_walls)
+        return fail(h, LBM_ERR_ARG, "state does not match this handle's configuration");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const char *p = static_cast<const char *>(buf) + sizeof hd;
+    TRY(copy_sync(h, h->pop[h->cur], p, popb, hipMemcpyHostToDevice));
+    p += popb;
+    TRY(copy_sync(h, h->own, p, sizeof(uint16_t) * h->N, hipMemcpyHostToDevice));
+    p += sizeof(uint16_t) * h->N;
+    TRY(copy_sync(h, h->wall_map, p, (size_t)h->N, hipMemcpyHostToDevice));
+    p += h->N;
+    TRY(copy_sync(h, h->tab[h->ts], p, tabb, hipMemcpyHostToDevice));
+    p += tabb;
+    TRY(copy_sync(h, h->tab[1 - h->ts], p, tabb, hipMemcpyHostToDevice));
+    p += tabb;
+    TRY(copy_sync(h, h->walls, p, wallb, hipMemcpyHostToDevice));
+    p += wallb;
+    TRY(copy_sync(h, h->acc, p, accb, hipMemcpyHostToDevice));
+    h->n_walls = hd.n_walls;
+    h->nb_state = hd.nb_state;
+    h->nb_next = hd.nb_next;
+    h->dirty = hd.dirty != 0;
+    h->steps_done = hd.steps_done;
+    h->initialized = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_info(lbm_handle h, lbm_info *info)
+{
+    if (!h || !info) return h ? fail(h, LBM_ERR_ARG, "NULL output") : LBM_ERR_ARG;
+    info->n_nodes = h->N;
+    info->n_bodies = h->nb_state;
+    info->n_walls = h->n_walls;
+    info->storage_bytes = h->sbytes;
+    info->steps_done = h->steps_done;
+    info->device_bytes = h->device_bytes;
+    return LBM_OK;
+}
+
+lbm_status lbm_count_fluid(lbm_handle h, int64_t *n_fluid)
+{
+    if (!h || !n_fluid) return h ? fail(h, LBM_ERR_ARG, "NULL output") : LBM_ERR_ARG;
+    TRY(ensure_scratch(h));
+    unsigned long long *d = reinterpret_cast<unsigned long long *>(h->scratch);
+    unsigned long long cnt = 0;
+    HIP_TRY(h, launch_zero(reinterpret_cast<double *>(d), 1, h->stream));
+    HIP_TRY(h, launch_count_fluid(h->own, h->N, d, h->stream));
+    TRY(copy_sync(h, &cnt, d, sizeof cnt, hipMemcpyDeviceToHost));
+    *n_fluid = (int64_t)cnt;
+    return LBM_OK;
+}
+
+lbm_status lbm_profile(lbm_handle h, int32_t enable)
+{
+    if (!h) return LBM_ERR_ARG;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (auto &p : h->prof_ev) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    h->prof_ev.clear();
+    h->prof = enable != 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_profile_read(lbm_handle h, double *ms_total, int64_t *launches)
+{
+    if (!h || !ms_total || !launches) return h ? fail(h, LBM_ERR_ARG, "NULL output") : LBM_ERR_ARG;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    double tot = 0.0;
+    for (auto &p : h->prof_ev) {
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, p.first, p.second));
+        tot += ms;
+    }
+    *ms_total = tot;
+    *launches = (int64_t)h->prof_ev.size();
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Internal interface between the C-ABI host layer (lbm_api.cpp) and the
+// gfx950 kernels (lbm_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int kQ = 19;
+
+// Owner map codes (uint16 per node).  Solid owners are ids below kVacated:
+// walls 0..n_walls-1, then spheres n_walls + b.  kVacated | id marks a node
+// that the previous geometry's sphere `id` covered while the map is being
+// rebuilt.  kNear marks fluid nodes with at least one solid neighbour among
+// the 18 links; kFluid marks the remaining fluid nodes.
+constexpr uint16_t kFluid = 0xFFFF;
+constexpr uint16_t kNear = 0xFFFE;
+constexpr uint16_t kVacated = 0x8000;
+constexpr int kMaxIds = 0x7FFE;
+
+// Stride of one sphere in a body table: X[3], V[3], Omega[3], R.
+constexpr int kBodyStride = 10;
+// Stride of one wall: U[3], ref[3].
+constexpr int kWallStride = 6;
+
+constexpr int kBlock = 256;
+
+// Unsigned 32-bit division by a runtime constant (round-down multiply-high).
+struct FastDiv {
+    uint32_t d, m, s;
+};
+FastDiv make_fastdiv(uint32_t d);
+
+struct StepArgs {
+    int nx, ny, nz;
+    int N;
+    FastDiv div_nx, div_ny;
+    float tau0, smag_k, rho0;       // smag_k = 18 sqrt(2) C^2
+    float fx, fy, fz;
+    int n_walls, nb, halfway;
+    int nblocks;
+    const uint16_t *own;
+    const void *src;
+    void *dst;
+    const double *bodies;
+    const double *walls;
+    double *acc;
+    int *flag;
+};
+
+struct GeomArgs {
+    int nx, ny, nz;
+    int N;
+    int n_walls;
+    const double *bodies;
+    int nb;
+    const double *bodies2;          // second table (new geometry) for the flag pass
+    int nb2;
+    uint16_t *own;
+    void *pop;                      // population buffer for the refill pass
+    float rho0;
+};
+
+// storage: 0 = fp32, 1 = fp16, 2 = bf16 deviations
+hipError_t launch_step(int storage, const StepArgs &a, hipStream_t s);
+hipError_t launch_walls_init(const uint8_t *wall, uint16_t *own, int N, hipStream_t s);
+hipError_t launch_flags_full(const GeomArgs &g, hipStream_t s);
+hipError_t launch_vacate(const GeomArgs &g, hipStream_t s);
+hipError_t launch_stamp(const GeomArgs &g, hipStream_t s);
+hipError_t launch_refill(int storage, const GeomArgs &g, hipStream_t s);
+hipError_t launch_flags_bodies(const GeomArgs &g, hipStream_t s);
+hipError_t launch_init_pop(int storage, const GeomArgs &g, const double *rho, const double *u,
+                           hipStream_t s);
+hipError_t launch_export_pop(int storage, const GeomArgs &g, const double *walls, int dir,
+                             double *out, hipStream_t s);
+hipError_t launch_import_pop(int storage, int N, int dir, float rho0, const double *in, void *pop,
+                             hipStream_t s);
+hipError_t launch_export_macro(int storage, const GeomArgs &g, const double *walls, double fx,
+                               double fy, double fz, double *rho, double *u, hipStream_t s);
+hipError_t launch_export_owner(const uint16_t *own, int N, int32_t *out, hipStream_t s);
+hipError_t launch_zero(double *p, int n, hipStream_t s);
+hipError_t launch_count_fluid(const uint16_t *own, int N, unsigned long long *count,
+                              hipStream_t s);
+
+}  // namespace lbm

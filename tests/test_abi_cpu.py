@@ -1,0 +1,141 @@
+"""Host-side checks of the C-ABI library (no device work).
+
+* the library loads and exports every function declared in include/lbm.h;
+* the ctypes struct layouts match the C compiler's (offsets and sizes);
+* argument errors are reported before any HIP call, with the documented codes;
+* the seeded generators are deterministic and honour their stated recipe.
+"""
+import ctypes as ct
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import lbm_workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1703_05158_amd as P
+    return P
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported(P):
+    names = _declared()
+    assert len(names) >= 20
+    lib = ct.CDLL(P.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in lbm.h but not exported"
+    assert sorted(P.EXPORTED) == names, "binding and header disagree"
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\b(lbm_[a-z_]+)\b", out))
+    assert set(names) <= exported
+
+
+def test_struct_layout_matches_c(P):
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "lbm.h"
+#define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+int main(void) {
+  printf("sizeof.lbm_config %zu\n", sizeof(lbm_config));
+  printf("sizeof.lbm_info %zu\n", sizeof(lbm_info));
+  O(lbm_config, nx); O(lbm_config, ny); O(lbm_config, nz); O(lbm_config, storage);
+  O(lbm_config, tau0); O(lbm_config, smag_c); O(lbm_config, rho0); O(lbm_config, body_force);
+  O(lbm_config, bb_mode); O(lbm_config, max_bodies); O(lbm_config, max_walls);
+  O(lbm_config, nan_guard_every); O(lbm_config, stream);
+  O(lbm_info, n_nodes); O(lbm_info, n_bodies); O(lbm_info, n_walls); O(lbm_info, storage_bytes);
+  O(lbm_info, steps_done); O(lbm_info, device_bytes);
+  return 0; }
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "l.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "l")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        lines = subprocess.run([exe], capture_output=True, text=True).stdout.split("\n")
+    got = dict(l.split() for l in lines if l)
+    assert int(got["sizeof.lbm_config"]) == ct.sizeof(P.LBMConfig)
+    assert int(got["sizeof.lbm_info"]) == ct.sizeof(P.LBMInfo)
+    for S, name in ((P.LBMConfig, "lbm_config"), (P.LBMInfo, "lbm_info")):
+        for f, _ in S._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(S, f).offset, f
+
+
+def _cfg(P, **kw):
+    base = dict(nx=8, ny=8, nz=8, tau0=0.6, smag_c=0.1)
+    base.update(kw)
+    return P.config(**base)
+
+
+@pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(tau0=0.5), dict(tau0=float("nan")),
+                                 dict(smag_c=-0.1), dict(rho0=0.0), dict(storage=3), dict(bb_mode=2),
+                                 dict(max_bodies=-1), dict(max_walls=256), dict(max_bodies=40000),
+                                 dict(nan_guard_every=-1), dict(body_force=(0, float("inf"), 0)),
+                                 dict(nx=2000, ny=2000, nz=2000)])
+def test_create_rejects_bad_config_before_device_work(P, bad):
+    with pytest.raises(P.LBMError) as e:
+        P.lbm_create(_cfg(P, **bad))
+    assert e.value.status == 1  # LBM_ERR_ARG, not OOM/HIP: validation precedes allocation
+
+
+def test_null_handle_and_pointers(P):
+    L = ct.CDLL(P.LIB_PATH)
+    L.lbm_last_error.restype = ct.c_char_p
+    L.lbm_last_error.argtypes = [ct.c_void_p]
+    assert L.lbm_last_error(None) == b"null lbm_handle"
+    assert L.lbm_create(None, None) == 1
+    assert L.lbm_step(None, ct.c_int32(1)) == 1
+    assert L.lbm_get_forces(None, None, None) == 1
+    assert L.lbm_set_bodies(None, ct.c_int32(0), None, None, None, None) == 1
+    assert L.lbm_get_info(None, None) == 1
+    L.lbm_destroy(None)  # ignored
+
+
+def test_version(P):
+    assert P.lbm_version() == 10000
+
+
+def test_generators_deterministic():
+    a, b = W.case_c0(), W.case_c0()
+    np.testing.assert_array_equal(a.X, b.X)
+    np.testing.assert_array_equal(a.u_init, b.u_init)
+    assert a.X.shape == (8, 3) and np.all(a.R == 4.0)
+    assert W.min_tie_gap(a.X, a.R, (32, 32, 32)) >= 1e-6
+    d = a.X[:, None, :] - a.X[None, :, :]
+    d -= 32 * np.round(d / 32)
+    dist = np.sqrt((d ** 2).sum(-1)) + np.eye(8) * 1e9
+    assert dist.min() >= 8.0 + 2.0 - 1e-12
+
+
+def test_duct_recipe():
+    c = W.case_duct(nx=48, ny=48, nz=160, n_spheres=150, orifice_z=120, orifice_r_in=14,
+                    orifice_gap=3, pack_z=(8, 110), seed=2)
+    w = c.wall_id
+    assert (w[:, :, 0] == 1).all() and (w[:, :, -1] == 1).all()
+    assert (w[:, 0, :] == 1).all() and (w[:, -1, :] == 1).all()
+    assert (w[0, 1:-1, 1:-1] == 2).all()
+    np.testing.assert_array_equal(c.wall_vel[1], [0, 0, 0.02])
+    plate = w[120]
+    yy, xx = np.meshgrid(np.arange(48), np.arange(48), indexing="ij")
+    r = np.hypot(xx - 23.5, yy - 23.5)
+    ann = (r >= 14) & (r < 17)
+    assert (plate[ann] == 0).all() and (plate[1:-1, 1:-1][~ann[1:-1, 1:-1]] == 3).all()
+    assert c.R.min() >= 2 and c.R.max() <= 6
+    lo = c.X - c.R[:, None]
+    hi = c.X + c.R[:, None]
+    assert lo[:, :2].min() >= 2 - 1e-12 and hi[:, :2].max() <= 46 + 1e-12
+    assert lo[:, 2].min() >= 8 - 1e-12 and hi[:, 2].max() <= 110 + 1e-12

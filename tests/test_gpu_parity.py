@@ -1,0 +1,271 @@
+"""GPU parity of the HIP step against the FP64 oracle, through the C ABI.
+
+Bar (FP32 storage): after the stated number of steps, populations within
+1e-5 relative at every fluid node and direction, forces and torques within
+1e-4 of the largest body force (torque) in norm.  Cases cover several
+workgroups with a ragged tail, static and drifting spheres (re-rasterised
+every step: vacate, stamp, refill of uncovered nodes, near-flag refresh),
+walls moving and static, halfway mode, a varying body count, the device
+body-table path, and the full 128x128x512 piston duct with 4000 spheres.
+"""
+import numpy as np
+import pytest
+
+import lbm_workloads as W
+
+from ._pair import advance, force_rel_err, make_pair, pop_rel_err
+
+pytestmark = pytest.mark.gpu
+
+POP_TOL = 1e-5
+FORCE_TOL = 1e-4
+
+_C1 = {}
+
+
+def _case_c1():
+    if "c" not in _C1:
+        _C1["c"] = W.case_c1()
+    return _C1["c"]
+
+
+@pytest.fixture(scope="module")
+def torch_stream():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _check(o, lat, pop_tol=POP_TOL, force_tol=FORCE_TOL):
+    pe = pop_rel_err(o, lat)
+    fe, te = force_rel_err(o, lat)
+    print(f"pop rel err {pe:.3e}  force {fe:.3e}  torque {te:.3e}", flush=True)
+    assert pe <= pop_tol
+    assert fe <= force_tol
+    assert te <= force_tol
+    return pe, fe, te
+
+
+def test_c0_parity_100_steps(torch_stream):
+    case = W.case_c0()
+    o, lat = make_pair(case, stream=torch_stream)
+    advance(o, lat, case, 0, 100)
+    _check(o, lat)
+    lat.close()
+
+
+def test_c0_halfway_parity(torch_stream):
+    case = W.case_c0()
+    o, lat = make_pair(case, halfway=True, stream=torch_stream)
+    advance(o, lat, case, 0, 40)
+    _check(o, lat)
+    lat.close()
+
+
+def test_drifting_spheres_ragged_box(torch_stream):
+    """37x29x41 (N not a multiple of 256), spheres translating and rotating fast
+    enough to cover and uncover nodes every few steps."""
+    case = W.case_box(n=(37, 29, 41), n_spheres=10, radius=(2.0, 5.0), tau0=0.62, smag_c=0.15,
+                      body_force=(2e-6, -1e-6, 5e-7), u_sigma=0.01, v_sigma=0.03, w_sigma=0.01,
+                      gap=1.5, seed=21, drift=True)
+    o, lat = make_pair(case, stream=torch_stream)
+    advance(o, lat, case, 0, 50)
+    _check(o, lat)
+    lat.close()
+
+
+def test_small_duct_drift_parity(torch_stream):
+    case = W.case_duct(nx=48, ny=48, nz=160, n_spheres=150, orifice_z=120, orifice_r_in=14,
+                       orifice_gap=3, pack_z=(8, 110), v_sigma=0.02, w_sigma=0.005, seed=2)
+    o, lat = make_pair(case, stream=torch_stream)
+    advance(o, lat, case, 0, 40)
+    _check(o, lat)
+    lat.close()
+
+
+def test_varying_body_count(torch_stream):
+    base = W.case_box(n=(30, 26, 34), n_spheres=6, radius=(2.0, 3.5), tau0=0.7, smag_c=0.12,
+                      u_sigma=0.01, v_sigma=0.01, w_sigma=0.003, gap=1.5, seed=8)
+    o, lat = make_pair(base, stream=torch_stream, max_bodies=6)
+    for n, k in enumerate([6, 4, 4, 0, 5, 6, 2], start=1):
+        X = np.mod(base.X[:k] + n * base.V[:k], [30, 26, 34])
+        args = (X, base.V[:k], base.Omega[:k], base.R[:k])
+        o.set_bodies(*args)
+        lat.set_bodies(*args)
+        o.step(1)
+        lat.step(1)
+        _check(o, lat)
+    lat.close()
+
+
+def test_device_body_table_matches_host(torch_stream):
+    import torch
+    case = W.case_box(n=(32, 24, 40), n_spheres=5, radius=(2.0, 4.0), v_sigma=0.02, w_sigma=0.01,
+                      seed=4, drift=True)
+    _, a = make_pair(case, stream=torch_stream)
+    _, b = make_pair(case, stream=torch_stream)
+    for n in range(1, 8):
+        X, V, Om, R = case.bodies_at(n)
+        a.set_bodies(X, V, Om, R)
+        tab = torch.tensor(np.concatenate([X, V, Om, R[:, None]], 1), dtype=torch.float64, device="cuda")
+        b.set_bodies_device(len(R), tab)
+        a.step(1)
+        b.step(1)
+        torch.cuda.synchronize()
+    np.testing.assert_array_equal(a.get_populations(), b.get_populations())
+    np.testing.assert_array_equal(a.get_owner(), b.get_owner())
+    a.close()
+    b.close()
+
+
+def test_owner_map_matches_oracle(torch_stream):
+    case = W.case_duct(nx=40, ny=36, nz=96, n_spheres=60, orifice_z=70, orifice_r_in=10,
+                       orifice_gap=3, pack_z=(6, 64), v_sigma=0.05, seed=5)
+    o, lat = make_pair(case, stream=torch_stream)
+    advance(o, lat, case, 0, 12)
+    own_o = o.owner()
+    np.testing.assert_array_equal(lat.get_owner(), own_o)
+    lat.close()
+
+
+@pytest.mark.parametrize("halfway", [False, True])
+def test_full_size_piston_duct_parity(torch_stream, halfway):
+    """128x128x512, 4000 drifting spheres, moving piston: 3 steps, the launch
+    configuration the benchmark times."""
+    import oracle
+    oracle.set_threads(16)
+    case = _case_c1()
+    o, lat = make_pair(case, halfway=halfway, stream=torch_stream)
+    advance(o, lat, case, 0, 3)
+    _check(o, lat)
+    lat.close()
+
+
+def test_couette_and_poiseuille_gpu(torch_stream):
+    from paper_1703_05158_amd import Lattice, config
+    H, U = 8, 0.01
+    wall = np.zeros((1, H + 2, 1), np.uint8)
+    wall[0, 0, 0], wall[0, H + 1, 0] = 1, 2
+    y = np.arange(1, H + 1)
+    lat = Lattice(config(1, H + 2, 1, 0.8, 0.0, max_walls=2, stream=torch_stream))
+    lat.set_walls(wall, [[-U, 0, 0], [U, 0, 0]])
+    lat.init_fields()
+    lat.step(3000)
+    _, u = lat.get_macro()
+    np.testing.assert_allclose(u[0, 0, 1:H + 1, 0], -U + 2 * U * (y - 0.5) / H, rtol=0, atol=2e-8)
+    lat.close()
+    tau = 0.5 + np.sqrt(3) / 4
+    Fx = 1e-6
+    lat = Lattice(config(1, H + 2, 1, tau, 0.0, body_force=(Fx, 0, 0), max_walls=2, stream=torch_stream))
+    lat.set_walls(wall, np.zeros((2, 3)))
+    lat.init_fields()
+    lat.step(6000)
+    _, u = lat.get_macro()
+    nu = (tau - 0.5) / 3
+    exact = Fx / (2 * nu) * (y - 0.5) * (H + 0.5 - y)
+    np.testing.assert_allclose(u[0, 0, 1:H + 1, 0], exact, rtol=2e-4)
+    F, _ = lat.get_forces()
+    np.testing.assert_allclose(F.sum(0)[0], Fx * H, rtol=2e-4)
+    lat.close()
+
+
+def test_mass_and_momentum_balance_gpu(torch_stream):
+    """Halfway links with moving spheres conserve mass; M_n - M_{n-1} =
+    N_fluid F - sum F_b (FP32 rounding level)."""
+    case = W.case_box(n=(40, 36, 44), n_spheres=8, radius=(2.5, 4.0), tau0=0.7, smag_c=0.1,
+                      body_force=(2e-5, 1e-5, -1e-5), u_sigma=0.01, v_sigma=0.01, w_sigma=0.003, seed=12)
+    from paper_1703_05158_amd import Lattice
+    lat = Lattice.from_case(case, bb_mode="halfway", stream=torch_stream)
+    own = lat.get_owner()
+    m = own < 0
+    import oracle
+    c, _, _ = oracle.tables()
+
+    def moments():
+        P = lat.get_populations()[:, m]
+        return P.sum(), c.T.astype(float) @ P.sum(1)
+    M0, J0 = moments()
+    nf = m.sum()
+    for _ in range(5):
+        lat.step(1)
+        M1, J1 = moments()
+        F, _ = lat.get_forces()
+        assert abs(M1 - M0) / M0 < 2e-7
+        np.testing.assert_allclose(J1 - J0, nf * np.array(case.body_force) - F.sum(0), rtol=0, atol=2e-4)
+        M0, J0 = M1, J1
+    lat.close()
+
+
+def test_state_checkpoint_resume_bitwise(torch_stream):
+    case = W.case_box(n=(30, 30, 30), n_spheres=5, radius=(2.0, 4.0), v_sigma=0.02, w_sigma=0.01,
+                      seed=6, drift=True)
+    from paper_1703_05158_amd import Lattice
+    lat = Lattice.from_case(case, stream=torch_stream)
+
+    def run(l, a, b):
+        for n in range(a, b):
+            l.set_bodies(*case.bodies_at(n))
+            l.step(1)
+    run(lat, 1, 6)
+    state = lat.get_state()
+    run(lat, 6, 12)
+    ref = lat.get_populations()
+    lat2 = Lattice.from_case(case, stream=torch_stream)
+    lat2.set_state(state)
+    run(lat2, 6, 12)
+    np.testing.assert_array_equal(lat2.get_populations(), ref)
+    lat.close()
+    lat2.close()
+
+
+def test_nan_guard_reports_unstable(torch_stream):
+    from paper_1703_05158_amd import LBMError, Lattice
+    case = W.case_box(n=(16, 16, 16), n_spheres=0, u_sigma=0.0, seed=0)
+    lat = Lattice.from_case(case, stream=torch_stream, nan_guard_every=1)
+    lat.step(2)
+    f = lat.get_populations()
+    # negate a 3x3x3 block: its centre pulls only negated values (rho = -1)
+    f[:, 2:5, 3:6, 4:7] = -f[:, 2:5, 3:6, 4:7]
+    lat.set_populations(f)
+    with pytest.raises(LBMError) as e:
+        lat.step(1)
+    assert e.value.status == 5
+    lat.close()
+
+
+def test_errors_on_device_handle(torch_stream):
+    from paper_1703_05158_amd import LBMError, Lattice, config
+    lat = Lattice(config(16, 16, 16, 0.6, 0.1, max_bodies=2, stream=torch_stream))
+    with pytest.raises(LBMError) as e:
+        lat.step(1)
+    assert e.value.status == 4                                   # before init
+    with pytest.raises(LBMError) as e:
+        lat.set_bodies(np.zeros((3, 3)) + 5, np.zeros((3, 3)), np.zeros((3, 3)), np.ones(3))
+    assert e.value.status == 6                                   # capacity
+    with pytest.raises(LBMError) as e:
+        lat.set_bodies([[5, 5, 5]], [[0, 0, 0]], [[0, 0, 0]], [7.5])
+    assert e.value.status == 1                                   # radius too large
+    with pytest.raises(LBMError) as e:
+        lat.set_bodies([[16.0, 5, 5]], [[0, 0, 0]], [[0, 0, 0]], [2.0])
+    assert e.value.status == 1                                   # centre outside the box
+    lat.init_fields()
+    with pytest.raises(LBMError) as e:
+        lat.set_walls(np.zeros((16, 16, 16), np.uint8), np.zeros((0, 3)))
+    assert e.value.status == 4                                   # walls after init
+    lat.step(3)
+    assert lat.info()["steps_done"] == 3
+    assert lat.count_fluid() == 16 ** 3
+    lat.close()
+
+
+def test_profile_counts_launches(torch_stream):
+    case = W.case_box(n=(32, 32, 32), n_spheres=2, seed=1)
+    from paper_1703_05158_amd import Lattice
+    lat = Lattice.from_case(case, stream=torch_stream)
+    lat.profile(True)
+    lat.step(7)
+    ms, n = lat.profile_read()
+    assert n == 7 and ms > 0
+    lat.profile(False)
+    lat.close()
