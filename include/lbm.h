@@ -80,7 +80,7 @@ typedef struct lbm_config {
     double body_force[3];      /* body-force density per fluid node per step (Guo forcing) */
     int32_t bb_mode;           /* lbm_bb_mode */
     int32_t max_bodies;        /* capacity of the sphere table, >= 0 */
-    int32_t max_walls;         /* capacity of the wall table, 0..255 */
+    int32_t max_walls;         /* capacity of the wall table, 0..16 */
     int32_t nan_guard_every;   /* 0 = off; k > 0: check every k steps (syncs) */
     void *stream;              /* hipStream_t to queue work on; NULL = null stream */
 } lbm_config;

@@ -33,7 +33,11 @@ struct lbm_ctx {
     bool dirty = false;                // tab[1-ts] set since the last step / init
     double *walls = nullptr;
     int n_walls = 0;
-    double *acc = nullptr;             // (max_bodies + max_walls) * 6
+    double *acc = nullptr;             // (max_bodies + max_walls) * 6: forces of the last step
+    int tile = kTile64x2x2;            // TileShape of the step kernel
+    int ntx = 0, nty = 0, ntz = 0, n_tiles = 0;
+    int *rec_n = nullptr, *rec_id = nullptr;
+    double *rec_v = nullptr, *wallpart = nullptr, *overflow = nullptr;
     int *flag = nullptr;
     int *flag_host = nullptr;
     double *scratch = nullptr;         // 4N doubles, export/import staging (lazy)
@@ -123,11 +127,10 @@ lbm_status rasterize_update(lbm_ctx *h)
     new_g.nb = h->nb_next;
     HIP_TRY(h, launch_vacate(old_g, h->stream));
     HIP_TRY(h, launch_stamp(new_g, h->stream));
-    HIP_TRY(h, launch_refill(h->cfg.storage, old_g, h->stream));
-    GeomArgs fl = old_g;
-    fl.bodies2 = new_g.bodies;
-    fl.nb2 = new_g.nb;
-    HIP_TRY(h, launch_flags_bodies(fl, h->stream));
+    GeomArgs st = old_g;
+    st.bodies2 = new_g.bodies;
+    st.nb2 = new_g.nb;
+    HIP_TRY(h, launch_settle(h->cfg.storage, st, h->stream));
     h->ts = 1 - h->ts;
     h->nb_state = h->nb_next;
     h->dirty = false;
@@ -182,7 +185,7 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
     if (!finite_all(c.body_force, 3)) return LBM_ERR_ARG;
     if (c.storage < 0 || c.storage > 2) return LBM_ERR_ARG;
     if (c.bb_mode < 0 || c.bb_mode > 1) return LBM_ERR_ARG;
-    if (c.max_bodies < 0 || c.max_walls < 0 || c.max_walls > 255) return LBM_ERR_ARG;
+    if (c.max_bodies < 0 || c.max_walls < 0 || c.max_walls > kMaxWalls) return LBM_ERR_ARG;
     if ((long long)c.max_bodies + c.max_walls > kMaxIds) return LBM_ERR_ARG;
     if (c.nan_guard_every < 0) return LBM_ERR_ARG;
 
@@ -198,6 +201,13 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
     };
     const size_t popb = (size_t)kQ * N * h->sbytes;
     const int nbt = c.max_bodies + c.max_walls;
+    // tile shape: 64 nodes along x unless x is a multiple of 32 but not of 64
+    h->tile = (c.nx % 64 != 0 && (c.nx % 32 == 0 || c.nx < 32)) ? kTile32x4x2 : kTile64x2x2;
+    const int TX = h->tile == kTile64x2x2 ? 64 : 32, TY = h->tile == kTile64x2x2 ? 2 : 4, TZ = 2;
+    h->ntx = (c.nx + TX - 1) / TX;
+    h->nty = (c.ny + TY - 1) / TY;
+    h->ntz = (c.nz + TZ - 1) / TZ;
+    h->n_tiles = h->ntx * h->nty * h->ntz;
     if (dalloc(h, &h->pop[0], popb) != hipSuccess || dalloc(h, &h->pop[1], popb) != hipSuccess ||
         dalloc(h, &h->own, sizeof(uint16_t) * N + 4) != hipSuccess ||
         dalloc(h, &h->wall_map, (size_t)N) != hipSuccess ||
@@ -205,6 +215,11 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         dalloc(h, &h->tab[1], sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->walls, sizeof(double) * kWallStride * std::max(c.max_walls, 1)) != hipSuccess ||
         dalloc(h, &h->acc, sizeof(double) * 6 * std::max(nbt, 1)) != hipSuccess ||
+        dalloc(h, &h->rec_n, sizeof(int) * (size_t)h->n_tiles) != hipSuccess ||
+        dalloc(h, &h->rec_id, sizeof(int) * (size_t)h->n_tiles * kRec) != hipSuccess ||
+        dalloc(h, &h->rec_v, sizeof(double) * 6 * (size_t)h->n_tiles * kRec) != hipSuccess ||
+        dalloc(h, &h->wallpart, sizeof(double) * 6 * (size_t)h->n_tiles * std::max(c.max_walls, 1)) != hipSuccess ||
+        dalloc(h, &h->overflow, sizeof(double) * 6 * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->flag, sizeof(int)) != hipSuccess)
         return bail(LBM_ERR_OOM);
     if (hipHostMalloc((void **)&h->pinned, sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
@@ -215,6 +230,7 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         hipMemsetAsync(h->pop[0], 0, popb, h->stream) != hipSuccess ||
         hipMemsetAsync(h->pop[1], 0, popb, h->stream) != hipSuccess ||
         hipMemsetAsync(h->acc, 0, sizeof(double) * 6 * std::max(nbt, 1), h->stream) != hipSuccess ||
+        hipMemsetAsync(h->overflow, 0, sizeof(double) * 6 * std::max(c.max_bodies, 1), h->stream) != hipSuccess ||
         hipMemsetAsync(h->flag, 0, sizeof(int), h->stream) != hipSuccess)
         return bail(LBM_ERR_HIP);
     if (rasterize_full(h) != LBM_OK) return bail(LBM_ERR_HIP);
@@ -232,7 +248,8 @@ void lbm_destroy(lbm_handle h)
         (void)hipEventDestroy(p.second);
     }
     void *dev[] = {h->pop[0], h->pop[1], h->own, h->wall_map, h->tab[0], h->tab[1],
-                   h->walls, h->acc, h->flag, h->scratch};
+                   h->walls, h->acc, h->flag, h->scratch, h->rec_n, h->rec_id, h->rec_v,
+                   h->wallpart, h->overflow};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (h->pinned) (void)hipHostFree(h->pinned);
@@ -377,8 +394,11 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
     a.ny = c.ny;
     a.nz = c.nz;
     a.N = h->N;
-    a.div_nx = make_fastdiv((uint32_t)c.nx);
-    a.div_ny = make_fastdiv((uint32_t)c.ny);
+    a.tile = h->tile;
+    a.ntx = h->ntx;
+    a.nty = h->nty;
+    a.ntz = h->ntz;
+    a.n_tiles = h->n_tiles;
     a.tau0 = (float)c.tau0;
     a.smag_k = (float)(18.0 * std::sqrt(2.0) * c.smag_c * c.smag_c);
     a.rho0 = (float)c.rho0;
@@ -386,10 +406,14 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
     a.fy = (float)c.body_force[1];
     a.fz = (float)c.body_force[2];
     a.halfway = c.bb_mode == LBM_BB_HALFWAY;
-    a.nblocks = (h->N + kBlock - 1) / kBlock;
     a.own = h->own;
     a.walls = h->walls;
-    a.acc = h->acc;
+    a.rec_n = h->rec_n;
+    a.rec_id = h->rec_id;
+    a.rec_v = h->rec_v;
+    a.wallpart = h->wallpart;
+    a.overflow = h->overflow;
+    a.out = h->acc;
     a.flag = c.nan_guard_every > 0 ? h->flag : nullptr;
     for (int s = 0; s < nsteps; ++s) {
         if (h->dirty && (st = rasterize_update(h)) != LBM_OK) return st;
@@ -398,7 +422,7 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
         a.bodies = h->tab[h->ts];
         a.src = h->pop[h->cur];
         a.dst = h->pop[1 - h->cur];
-        HIP_TRY(h, launch_zero(h->acc, 6 * (a.nb + a.n_walls), h->stream));
+        HIP_TRY(h, launch_links(c.storage, a, h->stream));
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (h->prof) {
             HIP_TRY(h, hipEventCreate(&e0));
@@ -410,6 +434,7 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
             HIP_TRY(h, hipEventRecord(e1, h->stream));
             h->prof_ev.emplace_back(e0, e1);
         }
+        HIP_TRY(h, launch_forces(a, h->stream));
         h->cur = 1 - h->cur;
         h->steps_done++;
         if (c.nan_guard_every > 0 && (h->steps_done % c.nan_guard_every == 0 || s == nsteps - 1)) {

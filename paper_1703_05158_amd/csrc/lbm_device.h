@@ -1,0 +1,123 @@
+// Device-side helpers shared by the gfx950 kernels: the D3Q19 tables of the
+// paper's Table 1, population storage formats, index arithmetic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace dev {
+
+// Table 1: c_i for i = 0..18.
+constexpr int CX[kQ] = {0, -1, 0, 0, -1, -1, -1, -1, 0, 0, 1, 0, 0, 1, 1, 1, 1, 0, 0};
+constexpr int CY[kQ] = {0, 0, -1, 0, -1, 1, 0, 0, -1, -1, 0, 1, 0, 1, -1, 0, 0, 1, 1};
+constexpr int CZ[kQ] = {0, 0, 0, -1, 0, 0, -1, 1, -1, 1, 0, 0, 1, 0, 0, 1, -1, 1, -1};
+
+constexpr uint64_t pack_dir(const int (&c)[kQ])
+{
+    uint64_t v = 0;
+    for (int i = 0; i < kQ; ++i) v |= (uint64_t)(c[i] + 1) << (2 * i);
+    return v;
+}
+constexpr uint64_t kPX = pack_dir(CX), kPY = pack_dir(CY), kPZ = pack_dir(CZ);
+
+// Runtime-indexed lookups (cold paths) without memory traffic.
+__device__ __forceinline__ int dcx(int i) { return (int)((kPX >> (2 * i)) & 3) - 1; }
+__device__ __forceinline__ int dcy(int i) { return (int)((kPY >> (2 * i)) & 3) - 1; }
+__device__ __forceinline__ int dcz(int i) { return (int)((kPZ >> (2 * i)) & 3) - 1; }
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i <= 9 ? i + 9 : i - 9); }
+
+// Weights: w0 = 1/3, axis directions (1,2,3,10,11,12) 1/18, others 1/36.
+__host__ __device__ constexpr double wgt(int i)
+{
+    return i == 0 ? 1.0 / 3.0 : (((0x1C0Eu >> i) & 1u) ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// Storage of deviations g = f - w rho0.
+template <int S> struct Store;
+template <> struct Store<0> {
+    using T = float;
+    static __device__ __forceinline__ float ld(const T *p) { return *p; }
+    static __device__ __forceinline__ void st(T *p, float v) { *p = v; }
+    static __device__ __forceinline__ float round(float v) { return v; }
+};
+template <> struct Store<1> {
+    using T = _Float16;
+    static __device__ __forceinline__ float ld(const T *p) { return (float)*p; }
+    static __device__ __forceinline__ void st(T *p, float v) { *p = (_Float16)v; }
+    static __device__ __forceinline__ float round(float v) { return (float)(_Float16)v; }
+};
+template <> struct Store<2> {  // bfloat16 as raw bits, round to nearest even
+    using T = uint16_t;
+    static __device__ __forceinline__ float ld(const T *p) { return __uint_as_float((uint32_t)*p << 16); }
+    static __device__ __forceinline__ uint16_t bits(float v)
+    {
+        const uint32_t u = __float_as_uint(v);
+        if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+        return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    }
+    static __device__ __forceinline__ void st(T *p, float v) { *p = bits(v); }
+    static __device__ __forceinline__ float round(float v) { return __uint_as_float((uint32_t)bits(v) << 16); }
+};
+
+// Element `e` of an array whose byte size fits in 32 bits: the offset is a
+// zero-extended 32-bit value, so the load can use a uniform base register.
+template <typename T>
+__device__ __forceinline__ const T *at(const T *base, uint32_t e)
+{
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (uint64_t)(e * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ T *at(T *base, uint32_t e)
+{
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (uint64_t)(e * (uint32_t)sizeof(T)));
+}
+
+__device__ __forceinline__ int wrap_add(int a, int d, int n)
+{
+    const int r = a + d;
+    return r < 0 ? r + n : (r >= n ? r - n : r);
+}
+
+// Wrap a coordinate known to lie in [-n, 2n).
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__device__ __forceinline__ double min_image(double d, double L)
+{
+    if (d > 0.5 * L) d -= L;
+    else if (d < -0.5 * L) d += L;
+    return d;
+}
+
+// A sphere the rasteriser accepts: radius in (0, min(n)/2 - 1), centre in the box.
+__device__ __forceinline__ bool body_ok(const double *B, int nx, int ny, int nz)
+{
+    const double lim = 0.5 * (double)min(nx, min(ny, nz)) - 1.0;
+    return B[9] > 0.0 && B[9] < lim && B[0] >= 0.0 && B[0] < nx && B[1] >= 0.0 && B[1] < ny &&
+           B[2] >= 0.0 && B[2] < nz;
+}
+
+// Deviation of the equilibrium at rho0 and velocity u from the rest state:
+// w_i rho0 (3 c.u + 4.5 (c.u)^2 - 1.5 u.u).
+__device__ __forceinline__ double eq_dev(int i, double rho0, double u0, double u1, double u2)
+{
+    const double cu = dcx(i) * u0 + dcy(i) * u1 + dcz(i) * u2;
+    return wgt(i) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * (u0 * u0 + u1 * u1 + u2 * u2));
+}
+
+// Rigid-body velocity V + Omega x r at node p, r the minimum image of p - X.
+__device__ __forceinline__ void sphere_velocity(const double *B, int px, int py, int pz, int nx, int ny, int nz,
+                                                double &u0, double &u1, double &u2)
+{
+    const double r0 = min_image((double)px - B[0], nx);
+    const double r1 = min_image((double)py - B[1], ny);
+    const double r2 = min_image((double)pz - B[2], nz);
+    u0 = B[3] + (B[7] * r2 - B[8] * r1);
+    u1 = B[4] + (B[8] * r0 - B[6] * r2);
+    u2 = B[5] + (B[6] * r1 - B[7] * r0);
+}
+
+}  // namespace dev
+}  // namespace lbm

@@ -1,0 +1,370 @@
+// Owner-map maintenance and state import/export kernels (gfx950).
+//
+// The owner map is kept incrementally when spheres move: vacate the previous
+// geometry's sphere nodes (tagging them kVacated | id), stamp the new
+// spheres with an atomic minimum (walls and lower sphere indices win), then
+// settle the neighbourhood of every old and new sphere: a node still tagged
+// kVacated was uncovered and is refilled with the equilibrium at rho0 and the
+// velocity it had as a solid (the solid-side Maxwell equilibrium of Sec. 2.3),
+// and every fluid node there gets its near-boundary flag recomputed.  One
+// workgroup per sphere walks the sphere's bounding box with an 8x8x4 thread
+// block.
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace lbm {
+namespace {
+
+using namespace dev;
+
+// |p - X|^2 <= R^2 with the minimum image, as a plain product-sum evaluated
+// left to right without fused multiply-add.
+__device__ __forceinline__ bool inside(const double *B, int px, int py, int pz, int nx, int ny, int nz)
+{
+    const double dx = min_image((double)px - B[0], nx);
+    const double dy = min_image((double)py - B[1], ny);
+    const double dz = min_image((double)pz - B[2], nz);
+    const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    return d2 <= __dmul_rn(B[9], B[9]);
+}
+
+struct Box {
+    int x0, y0, z0, ex, ey, ez;
+};
+
+__device__ __forceinline__ Box body_box(const double *B, int pad)
+{
+    Box b;
+    b.x0 = (int)ceil(B[0] - B[9]) - pad;
+    b.y0 = (int)ceil(B[1] - B[9]) - pad;
+    b.z0 = (int)ceil(B[2] - B[9]) - pad;
+    b.ex = (int)floor(B[0] + B[9]) + pad - b.x0 + 1;
+    b.ey = (int)floor(B[1] + B[9]) + pad - b.y0 + 1;
+    b.ez = (int)floor(B[2] + B[9]) + pad - b.z0 + 1;
+    return b;
+}
+
+// Visit every node of a body's box with a (8, 8, 4) workgroup.
+template <typename F>
+__device__ __forceinline__ void for_box(const Box &bx, int nx, int ny, int nz, F &&f)
+{
+    for (int kz = threadIdx.z; kz < bx.ez; kz += 4) {
+        const int pz = wrap1(bx.z0 + kz, nz);
+        for (int ky = threadIdx.y; ky < bx.ey; ky += 8) {
+            const int py = wrap1(bx.y0 + ky, ny);
+            for (int kx = threadIdx.x; kx < bx.ex; kx += 8) {
+                const int px = wrap1(bx.x0 + kx, nx);
+                f(px, py, pz, px + nx * (py + ny * pz));
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void atomic_min_u16(uint16_t *addr, uint16_t val)
+{
+    unsigned int *w = (unsigned int *)((uintptr_t)addr & ~(uintptr_t)3);
+    const unsigned int sh = ((uintptr_t)addr & 2) ? 16u : 0u;
+    unsigned int old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (true) {
+        const unsigned int cur = (old >> sh) & 0xffffu;
+        if (cur <= val) return;
+        const unsigned int nw = (old & ~(0xffffu << sh)) | ((unsigned int)val << sh);
+        const unsigned int prev = atomicCAS(w, old, nw);
+        if (prev == old) return;
+        old = prev;
+    }
+}
+
+// kNear if one of the 18 neighbours is solid, else kFluid.
+__device__ __forceinline__ uint16_t fluid_flag(const uint16_t *own, int x, int y, int z, int nx, int ny, int nz)
+{
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+        const int s = wrap_add(x, CX[i], nx) + nx * (wrap_add(y, CY[i], ny) + ny * wrap_add(z, CZ[i], nz));
+        if (own[s] < kVacated) return kNear;
+    }
+    return kFluid;
+}
+
+__global__ __launch_bounds__(kBlock) void k_walls_init(const uint8_t *wall, uint16_t *own, int N)
+{
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n < N) own[n] = wall[n] ? (uint16_t)(wall[n] - 1) : kFluid;
+}
+
+__global__ __launch_bounds__(kBlock) void k_flags_full(GeomArgs g)
+{
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    const uint16_t o = g.own[n];
+    if (o < kNear) return;
+    const int x = n % g.nx, y = (n / g.nx) % g.ny, z = n / (g.nx * g.ny);
+    const uint16_t f = fluid_flag(g.own, x, y, z, g.nx, g.ny, g.nz);
+    if (f != o) g.own[n] = f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_vacate(GeomArgs g)
+{
+    const double *B = g.bodies + blockIdx.x * kBodyStride;
+    if (!body_ok(B, g.nx, g.ny, g.nz)) return;
+    const uint16_t id = (uint16_t)(g.n_walls + blockIdx.x);
+    uint16_t *own = g.own;
+    for_box(body_box(B, 0), g.nx, g.ny, g.nz, [&](int, int, int, int n) {
+        if (own[n] == id) own[n] = (uint16_t)(kVacated | id);
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void k_stamp(GeomArgs g)
+{
+    const double *B = g.bodies + blockIdx.x * kBodyStride;
+    if (!body_ok(B, g.nx, g.ny, g.nz)) return;
+    const uint16_t id = (uint16_t)(g.n_walls + blockIdx.x);
+    uint16_t *own = g.own;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    for_box(body_box(B, 0), nx, ny, nz, [&](int px, int py, int pz, int n) {
+        if (inside(B, px, py, pz, nx, ny, nz)) atomic_min_u16(own + n, id);
+    });
+}
+
+// Refill uncovered nodes and refresh near flags around old (blocks < nb)
+// and new (blocks >= nb) spheres.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_settle(GeomArgs g)
+{
+    using St = Store<S>;
+    typename St::T *pop = static_cast<typename St::T *>(g.pop);
+    const int j = blockIdx.x;
+    const double *B = j < g.nb ? g.bodies + j * kBodyStride : g.bodies2 + (j - g.nb) * kBodyStride;
+    if (!body_ok(B, g.nx, g.ny, g.nz)) return;
+    uint16_t *own = g.own;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    for_box(body_box(B, 1), nx, ny, nz, [&](int px, int py, int pz, int n) {
+        const uint16_t o = own[n];
+        if (o >= kNear) {
+            const uint16_t f = fluid_flag(own, px, py, pz, nx, ny, nz);
+            if (f != o) own[n] = f;
+        } else if (o & kVacated) {
+            // uncovered: equilibrium at rho0 and the old solid velocity
+            const double *Bo = g.bodies + ((o & 0x7fff) - g.n_walls) * kBodyStride;
+            double u0, u1, u2;
+            sphere_velocity(Bo, px, py, pz, nx, ny, nz, u0, u1, u2);
+            for (int i = 0; i < kQ; ++i) St::st(pop + (size_t)i * g.N + n, (float)eq_dev(i, g.rho0, u0, u1, u2));
+            own[n] = fluid_flag(own, px, py, pz, nx, ny, nz);
+        }
+    });
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_init_pop(GeomArgs g, const double *rho, const double *u)
+{
+    using St = Store<S>;
+    typename St::T *pop = static_cast<typename St::T *>(g.pop);
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    const size_t N = (size_t)g.N;
+    if (g.own[n] < kNear) {
+        for (int i = 0; i < kQ; ++i) St::st(pop + i * N + n, 0.0f);
+        return;
+    }
+    const double r = rho ? rho[n] : (double)g.rho0;
+    const double u0 = u ? u[n] : 0.0, u1 = u ? u[N + n] : 0.0, u2 = u ? u[2 * N + n] : 0.0;
+    const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+    for (int i = 0; i < kQ; ++i) {
+        const double cu = dcx(i) * u0 + dcy(i) * u1 + dcz(i) * u2;
+        const double dev = wgt(i) * (r - (double)g.rho0) + wgt(i) * r * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        St::st(pop + i * N + n, (float)dev);
+    }
+}
+
+__device__ __forceinline__ void solid_velocity(const GeomArgs &g, const double *walls, uint16_t o, int px, int py,
+                                               int pz, double &u0, double &u1, double &u2)
+{
+    if (o < g.n_walls) {
+        u0 = walls[o * kWallStride];
+        u1 = walls[o * kWallStride + 1];
+        u2 = walls[o * kWallStride + 2];
+    } else {
+        sphere_velocity(g.bodies + (o - g.n_walls) * kBodyStride, px, py, pz, g.nx, g.ny, g.nz, u0, u1, u2);
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_export_pop(GeomArgs g, const double *walls, int dir, double *out)
+{
+    using St = Store<S>;
+    const typename St::T *pop = static_cast<const typename St::T *>(g.pop);
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    const uint16_t o = g.own[n];
+    if (o >= kNear) {
+        out[n] = (double)St::ld(pop + (size_t)dir * g.N + n) + wgt(dir) * (double)g.rho0;
+        return;
+    }
+    const int px = n % g.nx, py = (n / g.nx) % g.ny, pz = n / (g.nx * g.ny);
+    double u0, u1, u2;
+    solid_velocity(g, walls, o, px, py, pz, u0, u1, u2);
+    out[n] = wgt(dir) * (double)g.rho0 + eq_dev(dir, g.rho0, u0, u1, u2);
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_import_pop(int N, int dir, float rho0, const double *in, void *popv)
+{
+    using St = Store<S>;
+    typename St::T *pop = static_cast<typename St::T *>(popv);
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n < N) St::st(pop + (size_t)dir * N + n, (float)(in[n] - wgt(dir) * (double)rho0));
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_export_macro(GeomArgs g, const double *walls, double fx, double fy,
+                                                         double fz, double *rho, double *u)
+{
+    using St = Store<S>;
+    const typename St::T *pop = static_cast<const typename St::T *>(g.pop);
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    const size_t N = (size_t)g.N;
+    const uint16_t o = g.own[n];
+    if (o >= kNear) {
+        double r = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
+        for (int i = 0; i < kQ; ++i) {
+            const double f = (double)St::ld(pop + i * N + n) + wgt(i) * (double)g.rho0;
+            r += f;
+            j0 += dcx(i) * f;
+            j1 += dcy(i) * f;
+            j2 += dcz(i) * f;
+        }
+        rho[n] = r;
+        u[n] = (j0 - 0.5 * fx) / r;
+        u[N + n] = (j1 - 0.5 * fy) / r;
+        u[2 * N + n] = (j2 - 0.5 * fz) / r;
+        return;
+    }
+    const int px = n % g.nx, py = (n / g.nx) % g.ny, pz = n / (g.nx * g.ny);
+    double u0, u1, u2;
+    solid_velocity(g, walls, o, px, py, pz, u0, u1, u2);
+    rho[n] = g.rho0;
+    u[n] = u0;
+    u[N + n] = u1;
+    u[2 * N + n] = u2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_export_owner(const uint16_t *own, int N, int32_t *out)
+{
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n < N) out[n] = own[n] >= kNear ? -1 : (int32_t)own[n];
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero(double *p, int n)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_fluid(const uint16_t *own, int N, unsigned long long *count)
+{
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    const unsigned long long mask = __ballot(n < N && own[n] >= kNear);
+    if (__lane_id() == 0 && mask) atomicAdd(count, (unsigned long long)__popcll(mask));
+}
+
+inline int nblk(long n) { return (int)((n + kBlock - 1) / kBlock); }
+const dim3 kBoxBlock(8, 8, 4);
+
+template <template <int> class K, typename... A>
+hipError_t dispatch(int storage, dim3 grid, dim3 block, hipStream_t s, A... args)
+{
+    switch (storage) {
+    case 0: hipLaunchKernelGGL(K<0>::fn, grid, block, 0, s, args...); break;
+    case 1: hipLaunchKernelGGL(K<1>::fn, grid, block, 0, s, args...); break;
+    case 2: hipLaunchKernelGGL(K<2>::fn, grid, block, 0, s, args...); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int S> struct SettleK { static constexpr auto fn = k_settle<S>; };
+template <int S> struct InitK { static constexpr auto fn = k_init_pop<S>; };
+template <int S> struct ExportK { static constexpr auto fn = k_export_pop<S>; };
+template <int S> struct ImportK { static constexpr auto fn = k_import_pop<S>; };
+template <int S> struct MacroK { static constexpr auto fn = k_export_macro<S>; };
+
+}  // namespace
+
+hipError_t launch_walls_init(const uint8_t *wall, uint16_t *own, int N, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_walls_init, dim3(nblk(N)), dim3(kBlock), 0, s, wall, own, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_flags_full(const GeomArgs &g, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flags_full, dim3(nblk(g.N)), dim3(kBlock), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_vacate(const GeomArgs &g, hipStream_t s)
+{
+    if (g.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vacate, dim3(g.nb), kBoxBlock, 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp(const GeomArgs &g, hipStream_t s)
+{
+    if (g.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stamp, dim3(g.nb), kBoxBlock, 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_settle(int storage, const GeomArgs &g, hipStream_t s)
+{
+    if (g.nb + g.nb2 <= 0) return hipSuccess;
+    return dispatch<SettleK>(storage, dim3(g.nb + g.nb2), kBoxBlock, s, g);
+}
+
+hipError_t launch_init_pop(int storage, const GeomArgs &g, const double *rho, const double *u, hipStream_t s)
+{
+    return dispatch<InitK>(storage, dim3(nblk(g.N)), dim3(kBlock), s, g, rho, u);
+}
+
+hipError_t launch_export_pop(int storage, const GeomArgs &g, const double *walls, int dir, double *out,
+                             hipStream_t s)
+{
+    return dispatch<ExportK>(storage, dim3(nblk(g.N)), dim3(kBlock), s, g, walls, dir, out);
+}
+
+hipError_t launch_import_pop(int storage, int N, int dir, float rho0, const double *in, void *pop, hipStream_t s)
+{
+    return dispatch<ImportK>(storage, dim3(nblk(N)), dim3(kBlock), s, N, dir, rho0, in, pop);
+}
+
+hipError_t launch_export_macro(int storage, const GeomArgs &g, const double *walls, double fx, double fy,
+                               double fz, double *rho, double *u, hipStream_t s)
+{
+    return dispatch<MacroK>(storage, dim3(nblk(g.N)), dim3(kBlock), s, g, walls, fx, fy, fz, rho, u);
+}
+
+hipError_t launch_export_owner(const uint16_t *own, int N, int32_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_export_owner, dim3(nblk(N)), dim3(kBlock), 0, s, own, N, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double *p, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(nblk(n)), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_fluid(const uint16_t *own, int N, unsigned long long *count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count_fluid, dim3(nblk(N)), dim3(kBlock), 0, s, own, N, count);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,5 +1,5 @@
 // Internal interface between the C-ABI host layer (lbm_api.cpp) and the
-// gfx950 kernels (lbm_kernels.hip).  Not installed; not part of the ABI.
+// gfx950 kernels (lbm_step.hip, lbm_geometry.hip).  Not part of the ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,33 +19,33 @@ constexpr uint16_t kNear = 0xFFFE;
 constexpr uint16_t kVacated = 0x8000;
 constexpr int kMaxIds = 0x7FFE;
 
-// Stride of one sphere in a body table: X[3], V[3], Omega[3], R.
-constexpr int kBodyStride = 10;
-// Stride of one wall: U[3], ref[3].
-constexpr int kWallStride = 6;
+constexpr int kBodyStride = 10;   // X[3], V[3], Omega[3], R
+constexpr int kWallStride = 6;    // U[3], ref[3]
+constexpr int kMaxWalls = 16;     // walls get dedicated per-tile force slots
+constexpr int kRec = 32;          // per-tile force records of spheres
+constexpr int kBlock = 256;       // threads of a step workgroup (one tile)
 
-constexpr int kBlock = 256;
-
-// Unsigned 32-bit division by a runtime constant (round-down multiply-high).
-struct FastDiv {
-    uint32_t d, m, s;
-};
-FastDiv make_fastdiv(uint32_t d);
+// Tile shapes of the step kernel (x extent; y and z fill 256 threads).
+enum TileShape { kTile64x2x2 = 0, kTile32x4x2 = 1 };
 
 struct StepArgs {
-    int nx, ny, nz;
-    int N;
-    FastDiv div_nx, div_ny;
-    float tau0, smag_k, rho0;       // smag_k = 18 sqrt(2) C^2
+    int nx, ny, nz, N;
+    int tile;                     // TileShape
+    int ntx, nty, ntz, n_tiles;
+    float tau0, smag_k, rho0;     // smag_k = 18 sqrt(2) C^2
     float fx, fy, fz;
     int n_walls, nb, halfway;
-    int nblocks;
     const uint16_t *own;
     const void *src;
     void *dst;
     const double *bodies;
     const double *walls;
-    double *acc;
+    int *rec_n;                   // [n_tiles]
+    int *rec_id;                  // [n_tiles][kRec]
+    double *rec_v;                // [n_tiles][kRec][6]
+    double *wallpart;             // [n_tiles][n_walls][6]
+    double *overflow;             // [max_bodies][6], zero between steps
+    double *out;                  // [nb + n_walls][6]
     int *flag;
 };
 
@@ -55,21 +55,23 @@ struct GeomArgs {
     int n_walls;
     const double *bodies;
     int nb;
-    const double *bodies2;          // second table (new geometry) for the flag pass
+    const double *bodies2;        // new geometry's table (settle pass)
     int nb2;
     uint16_t *own;
-    void *pop;                      // population buffer for the refill pass
+    void *pop;
     float rho0;
 };
 
 // storage: 0 = fp32, 1 = fp16, 2 = bf16 deviations
+hipError_t launch_links(int storage, const StepArgs &a, hipStream_t s);
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t s);
+hipError_t launch_forces(const StepArgs &a, hipStream_t s);
+
 hipError_t launch_walls_init(const uint8_t *wall, uint16_t *own, int N, hipStream_t s);
 hipError_t launch_flags_full(const GeomArgs &g, hipStream_t s);
 hipError_t launch_vacate(const GeomArgs &g, hipStream_t s);
 hipError_t launch_stamp(const GeomArgs &g, hipStream_t s);
-hipError_t launch_refill(int storage, const GeomArgs &g, hipStream_t s);
-hipError_t launch_flags_bodies(const GeomArgs &g, hipStream_t s);
+hipError_t launch_settle(int storage, const GeomArgs &g, hipStream_t s);
 hipError_t launch_init_pop(int storage, const GeomArgs &g, const double *rho, const double *u,
                            hipStream_t s);
 hipError_t launch_export_pop(int storage, const GeomArgs &g, const double *walls, int dir,
