@@ -22,10 +22,12 @@ struct lbm_ctx {
     lbm_config cfg{};
     hipStream_t stream = nullptr;
     int N = 0;
+    int Ns = 0;                        // stride between the 19 direction arrays
     int sbytes = 4;
     void *pop[2] = {nullptr, nullptr};
     int cur = 0;                       // pop[cur] holds the current (post-collision) state
     uint16_t *own = nullptr;
+    uint32_t *nmask = nullptr;
     uint8_t *wall_map = nullptr;
     double *tab[2] = {nullptr, nullptr};
     int ts = 0;                        // tab[ts]: bodies of the current state's geometry
@@ -96,12 +98,14 @@ GeomArgs geom(const lbm_ctx *h)
     g.ny = h->cfg.ny;
     g.nz = h->cfg.nz;
     g.N = h->N;
+    g.Ns = h->Ns;
     g.n_walls = h->n_walls;
     g.bodies = h->tab[h->ts];
     g.nb = h->nb_state;
     g.bodies2 = h->tab[1 - h->ts];
     g.nb2 = 0;
     g.own = h->own;
+    g.nmask = h->nmask;
     g.pop = h->pop[h->cur];
     g.rho0 = (float)h->cfg.rho0;
     return g;
@@ -136,6 +140,11 @@ lbm_status rasterize_update(lbm_ctx *h)
     h->dirty = false;
     return LBM_OK;
 }
+
+// Direction arrays start at staggered offsets: with a power-of-two node count
+// all 38 read/write streams of the step would otherwise sit at addresses
+// congruent modulo a large power of two.
+int pop_stride(int N) { return ((N + 63) / 64) * 64 + 1088; }
 
 lbm_status check_ready(lbm_ctx *h)
 {
@@ -194,12 +203,13 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
     h->cfg = c;
     h->stream = (hipStream_t)c.stream;
     h->N = (int)N;
+    h->Ns = pop_stride(h->N);
     h->sbytes = c.storage == 0 ? 4 : 2;
     auto bail = [&](lbm_status st) {
         lbm_destroy(h);
         return st;
     };
-    const size_t popb = (size_t)kQ * N * h->sbytes;
+    const size_t popb = (size_t)kQ * h->Ns * h->sbytes;
     const int nbt = c.max_bodies + c.max_walls;
     // tile shape: 64 nodes along x unless x is a multiple of 32 but not of 64
     h->tile = (c.nx % 64 != 0 && (c.nx % 32 == 0 || c.nx < 32)) ? kTile32x4x2 : kTile64x2x2;
@@ -210,6 +220,7 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
     h->n_tiles = h->ntx * h->nty * h->ntz;
     if (dalloc(h, &h->pop[0], popb) != hipSuccess || dalloc(h, &h->pop[1], popb) != hipSuccess ||
         dalloc(h, &h->own, sizeof(uint16_t) * N + 4) != hipSuccess ||
+        dalloc(h, &h->nmask, sizeof(uint32_t) * N) != hipSuccess ||
         dalloc(h, &h->wall_map, (size_t)N) != hipSuccess ||
         dalloc(h, &h->tab[0], sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->tab[1], sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
@@ -247,7 +258,7 @@ void lbm_destroy(lbm_handle h)
         (void)hipEventDestroy(p.first);
         (void)hipEventDestroy(p.second);
     }
-    void *dev[] = {h->pop[0], h->pop[1], h->own, h->wall_map, h->tab[0], h->tab[1],
+    void *dev[] = {h->pop[0], h->pop[1], h->own, h->nmask, h->wall_map, h->tab[0], h->tab[1],
                    h->walls, h->acc, h->flag, h->scratch, h->rec_n, h->rec_id, h->rec_v,
                    h->wallpart, h->overflow};
     for (void *p : dev)
@@ -394,6 +405,7 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
     a.ny = c.ny;
     a.nz = c.nz;
     a.N = h->N;
+    a.Ns = h->Ns;
     a.tile = h->tile;
     a.ntx = h->ntx;
     a.nty = h->nty;
@@ -407,6 +419,7 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
     a.fz = (float)c.body_force[2];
     a.halfway = c.bb_mode == LBM_BB_HALFWAY;
     a.own = h->own;
+    a.nmask = h->nmask;
     a.walls = h->walls;
     a.rec_n = h->rec_n;
     a.rec_id = h->rec_id;
@@ -422,7 +435,6 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
         a.bodies = h->tab[h->ts];
         a.src = h->pop[h->cur];
         a.dst = h->pop[1 - h->cur];
-        HIP_TRY(h, launch_links(c.storage, a, h->stream));
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (h->prof) {
             HIP_TRY(h, hipEventCreate(&e0));
@@ -503,7 +515,7 @@ lbm_status lbm_set_populations(lbm_handle h, const double *f)
     if ((st = ensure_scratch(h)) != LBM_OK) return st;
     for (int i = 0; i < kQ; ++i) {
         TRY(copy_sync(h, h->scratch, f + (size_t)i * h->N, sizeof(double) * h->N, hipMemcpyHostToDevice));
-        HIP_TRY(h, launch_import_pop(h->cfg.storage, h->N, i, (float)h->cfg.rho0, h->scratch, h->pop[h->cur],
+        HIP_TRY(h, launch_import_pop(h->cfg.storage, h->N, h->Ns, i, (float)h->cfg.rho0, h->scratch, h->pop[h->cur],
                                      h->stream));
     }
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -548,7 +560,7 @@ lbm_status lbm_get_state(lbm_handle h, void *buf, size_t *bytes)
     if (!h || !bytes) return h ? fail(h, LBM_ERR_ARG, "NULL size") : LBM_ERR_ARG;
     lbm_status st = check_ready(h);
     if (st != LBM_OK) return st;
-    const size_t popb = (size_t)kQ * h->N * h->sbytes;
+    const size_t popb = (size_t)kQ * h->Ns * h->sbytes;
     const size_t tabb = sizeof(double) * kBodyStride * std::max(h->cfg.max_bodies, 1);
     const size_t wallb = sizeof(double) * kWallStride * std::max(h->cfg.max_walls, 1);
     const size_t accb = sizeof(double) * 6 * std::max(h->cfg.max_bodies + h->cfg.max_walls, 1);
@@ -596,7 +608,7 @@ lbm_status lbm_get_state(lbm_handle h, void *buf, size_t *bytes)
 lbm_status lbm_set_state(lbm_handle h, const void *buf, size_t bytes)
 {
     if (!h || !buf) return h ? fail(h, LBM_ERR_ARG, "NULL buffer") : LBM_ERR_ARG;
-    const size_t popb = (size_t)kQ * h->N * h->sbytes;
+    const size_t popb = (size_t)kQ * h->Ns * h->sbytes;
     const size_t tabb = sizeof(double) * kBodyStride * std::max(h->cfg.max_bodies, 1);
     const size_t wallb = sizeof(double) * kWallStride * std::max(h->cfg.max_walls, 1);
     const size_t accb = sizeof(double) * 6 * std::max(h->cfg.max_bodies + h->cfg.max_walls, 1);

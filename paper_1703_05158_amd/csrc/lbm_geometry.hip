@@ -78,15 +78,17 @@ __device__ __forceinline__ void atomic_min_u16(uint16_t *addr, uint16_t val)
     }
 }
 
-// kNear if one of the 18 neighbours is solid, else kFluid.
-__device__ __forceinline__ uint16_t fluid_flag(const uint16_t *own, int x, int y, int z, int nx, int ny, int nz)
+// Solid-link mask of a fluid node: bit i set when the pull source x - c_i
+// is solid (kVacated nodes count as fluid: they are about to be refilled).
+__device__ __forceinline__ uint32_t link_mask(const uint16_t *own, int x, int y, int z, int nx, int ny, int nz)
 {
+    uint32_t m = 0;
 #pragma unroll
     for (int i = 1; i < kQ; ++i) {
-        const int s = wrap_add(x, CX[i], nx) + nx * (wrap_add(y, CY[i], ny) + ny * wrap_add(z, CZ[i], nz));
-        if (own[s] < kVacated) return kNear;
+        const int s = wrap_add(x, -CX[i], nx) + nx * (wrap_add(y, -CY[i], ny) + ny * wrap_add(z, -CZ[i], nz));
+        if (own[s] < kVacated) m |= 1u << i;
     }
-    return kFluid;
+    return m;
 }
 
 __global__ __launch_bounds__(kBlock) void k_walls_init(const uint8_t *wall, uint16_t *own, int N)
@@ -102,7 +104,9 @@ __global__ __launch_bounds__(kBlock) void k_flags_full(GeomArgs g)
     const uint16_t o = g.own[n];
     if (o < kNear) return;
     const int x = n % g.nx, y = (n / g.nx) % g.ny, z = n / (g.nx * g.ny);
-    const uint16_t f = fluid_flag(g.own, x, y, z, g.nx, g.ny, g.nz);
+    const uint32_t m = link_mask(g.own, x, y, z, g.nx, g.ny, g.nz);
+    g.nmask[n] = m;
+    const uint16_t f = m ? kNear : kFluid;
     if (f != o) g.own[n] = f;
 }
 
@@ -144,15 +148,19 @@ __global__ __launch_bounds__(kBlock) void k_settle(GeomArgs g)
     for_box(body_box(B, 1), nx, ny, nz, [&](int px, int py, int pz, int n) {
         const uint16_t o = own[n];
         if (o >= kNear) {
-            const uint16_t f = fluid_flag(own, px, py, pz, nx, ny, nz);
+            const uint32_t msk = link_mask(own, px, py, pz, nx, ny, nz);
+            g.nmask[n] = msk;
+            const uint16_t f = msk ? kNear : kFluid;
             if (f != o) own[n] = f;
         } else if (o & kVacated) {
             // uncovered: equilibrium at rho0 and the old solid velocity
             const double *Bo = g.bodies + ((o & 0x7fff) - g.n_walls) * kBodyStride;
             double u0, u1, u2;
             sphere_velocity(Bo, px, py, pz, nx, ny, nz, u0, u1, u2);
-            for (int i = 0; i < kQ; ++i) St::st(pop + (size_t)i * g.N + n, (float)eq_dev(i, g.rho0, u0, u1, u2));
-            own[n] = fluid_flag(own, px, py, pz, nx, ny, nz);
+            for (int i = 0; i < kQ; ++i) St::st(pop + (size_t)i * g.Ns + n, (float)eq_dev(i, g.rho0, u0, u1, u2));
+            const uint32_t msk = link_mask(own, px, py, pz, nx, ny, nz);
+            g.nmask[n] = msk;
+            own[n] = msk ? kNear : kFluid;
         }
     });
 }
@@ -166,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_init_pop(GeomArgs g, const double *r
     if (n >= g.N) return;
     const size_t N = (size_t)g.N;
     if (g.own[n] < kNear) {
-        for (int i = 0; i < kQ; ++i) St::st(pop + i * N + n, 0.0f);
+        for (int i = 0; i < kQ; ++i) St::st(pop + i * (size_t)g.Ns + n, 0.0f);
         return;
     }
     const double r = rho ? rho[n] : (double)g.rho0;
@@ -175,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_init_pop(GeomArgs g, const double *r
     for (int i = 0; i < kQ; ++i) {
         const double cu = dcx(i) * u0 + dcy(i) * u1 + dcz(i) * u2;
         const double dev = wgt(i) * (r - (double)g.rho0) + wgt(i) * r * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        St::st(pop + i * N + n, (float)dev);
+        St::st(pop + i * (size_t)g.Ns + n, (float)dev);
     }
 }
 
@@ -200,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_export_pop(GeomArgs g, const double 
     if (n >= g.N) return;
     const uint16_t o = g.own[n];
     if (o >= kNear) {
-        out[n] = (double)St::ld(pop + (size_t)dir * g.N + n) + wgt(dir) * (double)g.rho0;
+        out[n] = (double)St::ld(pop + (size_t)dir * g.Ns + n) + wgt(dir) * (double)g.rho0;
         return;
     }
     const int px = n % g.nx, py = (n / g.nx) % g.ny, pz = n / (g.nx * g.ny);
@@ -210,12 +218,12 @@ __global__ __launch_bounds__(kBlock) void k_export_pop(GeomArgs g, const double 
 }
 
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_import_pop(int N, int dir, float rho0, const double *in, void *popv)
+__global__ __launch_bounds__(kBlock) void k_import_pop(int N, int Ns, int dir, float rho0, const double *in, void *popv)
 {
     using St = Store<S>;
     typename St::T *pop = static_cast<typename St::T *>(popv);
     const int n = blockIdx.x * kBlock + threadIdx.x;
-    if (n < N) St::st(pop + (size_t)dir * N + n, (float)(in[n] - wgt(dir) * (double)rho0));
+    if (n < N) St::st(pop + (size_t)dir * Ns + n, (float)(in[n] - wgt(dir) * (double)rho0));
 }
 
 template <int S>
@@ -231,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_export_macro(GeomArgs g, const doubl
     if (o >= kNear) {
         double r = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
         for (int i = 0; i < kQ; ++i) {
-            const double f = (double)St::ld(pop + i * N + n) + wgt(i) * (double)g.rho0;
+            const double f = (double)St::ld(pop + i * (size_t)g.Ns + n) + wgt(i) * (double)g.rho0;
             r += f;
             j0 += dcx(i) * f;
             j1 += dcy(i) * f;
@@ -337,9 +345,10 @@ hipError_t launch_export_pop(int storage, const GeomArgs &g, const double *walls
     return dispatch<ExportK>(storage, dim3(nblk(g.N)), dim3(kBlock), s, g, walls, dir, out);
 }
 
-hipError_t launch_import_pop(int storage, int N, int dir, float rho0, const double *in, void *pop, hipStream_t s)
+hipError_t launch_import_pop(int storage, int N, int Ns, int dir, float rho0, const double *in, void *pop,
+                             hipStream_t s)
 {
-    return dispatch<ImportK>(storage, dim3(nblk(N)), dim3(kBlock), s, N, dir, rho0, in, pop);
+    return dispatch<ImportK>(storage, dim3(nblk(N)), dim3(kBlock), s, N, Ns, dir, rho0, in, pop);
 }
 
 hipError_t launch_export_macro(int storage, const GeomArgs &g, const double *walls, double fx, double fy,

@@ -13,7 +13,9 @@ constexpr int kQ = 19;
 // walls 0..n_walls-1, then spheres n_walls + b.  kVacated | id marks a node
 // that the previous geometry's sphere `id` covered while the map is being
 // rebuilt.  kNear marks fluid nodes with at least one solid neighbour among
-// the 18 links; kFluid marks the remaining fluid nodes.
+// the 18 links; kFluid marks the remaining fluid nodes.  For kNear nodes a
+// separate uint32 per node holds the solid-link mask: bit i set when the
+// pull source x - c_i is solid.
 constexpr uint16_t kFluid = 0xFFFF;
 constexpr uint16_t kNear = 0xFFFE;
 constexpr uint16_t kVacated = 0x8000;
@@ -30,12 +32,14 @@ enum TileShape { kTile64x2x2 = 0, kTile32x4x2 = 1 };
 
 struct StepArgs {
     int nx, ny, nz, N;
+    int Ns;                       // stride between direction arrays (elements, >= N)
     int tile;                     // TileShape
     int ntx, nty, ntz, n_tiles;
     float tau0, smag_k, rho0;     // smag_k = 18 sqrt(2) C^2
     float fx, fy, fz;
     int n_walls, nb, halfway;
     const uint16_t *own;
+    const uint32_t *nmask;        // solid-link mask of near-boundary nodes
     const void *src;
     void *dst;
     const double *bodies;
@@ -52,18 +56,19 @@ struct StepArgs {
 struct GeomArgs {
     int nx, ny, nz;
     int N;
+    int Ns;                       // stride between direction arrays
     int n_walls;
     const double *bodies;
     int nb;
     const double *bodies2;        // new geometry's table (settle pass)
     int nb2;
     uint16_t *own;
+    uint32_t *nmask;
     void *pop;
     float rho0;
 };
 
 // storage: 0 = fp32, 1 = fp16, 2 = bf16 deviations
-hipError_t launch_links(int storage, const StepArgs &a, hipStream_t s);
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t s);
 hipError_t launch_forces(const StepArgs &a, hipStream_t s);
 
@@ -76,7 +81,7 @@ hipError_t launch_init_pop(int storage, const GeomArgs &g, const double *rho, co
                            hipStream_t s);
 hipError_t launch_export_pop(int storage, const GeomArgs &g, const double *walls, int dir,
                              double *out, hipStream_t s);
-hipError_t launch_import_pop(int storage, int N, int dir, float rho0, const double *in, void *pop,
+hipError_t launch_import_pop(int storage, int N, int Ns, int dir, float rho0, const double *in, void *pop,
                              hipStream_t s);
 hipError_t launch_export_macro(int storage, const GeomArgs &g, const double *walls, double fx,
                                double fy, double fz, double *rho, double *u, hipStream_t s);
