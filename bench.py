@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 METRIC = "MLUPS and % of HBM roofline; mixed-precision vs FP32 at stated error"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_piston_duct_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1703_05158_amd", "csrc", "lbm_kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_1703_05158_amd", "csrc", "lbm_step.hip")
 
 
 def kernel_sha():
@@ -71,9 +71,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--static", action="store_true", help="bodies fixed (no per-step re-rasterisation)")
-    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle sample steps (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=15, help="oracle sample steps (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("OMP_NUM_THREADS", "16")))
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (HBM counter scale reference)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        torch.cuda.set_device(0)
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": a.numel() * 4, "bytes_written": a.numel() * 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU "
               "sharding of this step is a design note, not a built path.", file=sys.stderr)

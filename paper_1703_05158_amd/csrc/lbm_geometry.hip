@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 namespace lbm {
 namespace {
 
@@ -274,9 +276,14 @@ __global__ __launch_bounds__(kBlock) void k_zero(double *p, int n)
 
 __global__ __launch_bounds__(kBlock) void k_count_fluid(const uint16_t *own, int N, unsigned long long *count)
 {
-    const int n = blockIdx.x * kBlock + threadIdx.x;
-    const unsigned long long mask = __ballot(n < N && own[n] >= kNear);
-    if (__lane_id() == 0 && mask) atomicAdd(count, (unsigned long long)__popcll(mask));
+    __shared__ unsigned int s_cnt;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    unsigned int c = 0;
+    for (int n = blockIdx.x * kBlock + threadIdx.x; n < N; n += gridDim.x * kBlock) c += own[n] >= kNear;
+    atomicAdd(&s_cnt, c);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt) atomicAdd(count, (unsigned long long)s_cnt);
 }
 
 inline int nblk(long n) { return (int)((n + kBlock - 1) / kBlock); }
@@ -372,7 +379,7 @@ hipError_t launch_zero(double *p, int n, hipStream_t s)
 
 hipError_t launch_count_fluid(const uint16_t *own, int N, unsigned long long *count, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_count_fluid, dim3(nblk(N)), dim3(kBlock), 0, s, own, N, count);
+    hipLaunchKernelGGL(k_count_fluid, dim3(std::min(nblk(N), 2048)), dim3(kBlock), 0, s, own, N, count);
     return hipGetLastError();
 }
 
