@@ -2,6 +2,7 @@
 // the per-step launch sequence.  Every entry point returns an lbm_status and
 // never throws across the C ABI.
 #include "lbm.h"
+#include "lbm_device.h"
 #include "lbm_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -27,7 +28,6 @@ struct lbm_ctx {
     void *pop[2] = {nullptr, nullptr};
     int cur = 0;                       // pop[cur] holds the current (post-collision) state
     uint16_t *own = nullptr;
-    uint32_t *nmask = nullptr;
     uint8_t *wall_map = nullptr;
     double *tab[2] = {nullptr, nullptr};
     int ts = 0;                        // tab[ts]: bodies of the current state's geometry
@@ -38,8 +38,13 @@ struct lbm_ctx {
     double *acc = nullptr;             // (max_bodies + max_walls) * 6: forces of the last step
     int tile = kTile64x2x2;            // TileShape of the step kernel
     int ntx = 0, nty = 0, ntz = 0, n_tiles = 0;
-    int *rec_n = nullptr, *rec_id = nullptr;
-    double *rec_v = nullptr, *wallpart = nullptr, *overflow = nullptr;
+    // wall links (fixed while the walls are): fluid nodes per (wall, direction),
+    // workgroup chunks, per-chunk sums, each wall's range of chunks
+    uint32_t *wl_node = nullptr;
+    int *wl_blk = nullptr, *wl_wblk = nullptr;
+    double *wl_part = nullptr;
+    int n_wblk = 0;
+    int64_t wl_bytes = 0;
     int *flag = nullptr;
     int *flag_host = nullptr;
     double *scratch = nullptr;         // 4N doubles, export/import staging (lazy)
@@ -102,22 +107,18 @@ GeomArgs geom(const lbm_ctx *h)
     g.n_walls = h->n_walls;
     g.bodies = h->tab[h->ts];
     g.nb = h->nb_state;
-    g.bodies2 = h->tab[1 - h->ts];
-    g.nb2 = 0;
     g.own = h->own;
-    g.nmask = h->nmask;
     g.pop = h->pop[h->cur];
     g.rho0 = (float)h->cfg.rho0;
     return g;
 }
 
-// Rebuild the whole owner map: walls, spheres of tab[ts], near flags.
+// Rebuild the whole owner map: walls, then the spheres of tab[ts].
 lbm_status rasterize_full(lbm_ctx *h)
 {
     GeomArgs g = geom(h);
     HIP_TRY(h, launch_walls_init(h->wall_map, h->own, h->N, h->stream));
     HIP_TRY(h, launch_stamp(g, h->stream));
-    HIP_TRY(h, launch_flags_full(g, h->stream));
     return LBM_OK;
 }
 
@@ -131,10 +132,7 @@ lbm_status rasterize_update(lbm_ctx *h)
     new_g.nb = h->nb_next;
     HIP_TRY(h, launch_vacate(old_g, h->stream));
     HIP_TRY(h, launch_stamp(new_g, h->stream));
-    GeomArgs st = old_g;
-    st.bodies2 = new_g.bodies;
-    st.nb2 = new_g.nb;
-    HIP_TRY(h, launch_settle(h->cfg.storage, st, h->stream));
+    HIP_TRY(h, launch_settle(h->cfg.storage, old_g, h->stream));
     h->ts = 1 - h->ts;
     h->nb_state = h->nb_next;
     h->dirty = false;
@@ -172,6 +170,74 @@ lbm_status copy_sync(lbm_ctx *h, void *dst, const void *src, size_t bytes, hipMe
         lbm_status st_ = (expr);         \
         if (st_ != LBM_OK) return st_;   \
     } while (0)
+
+void free_wall_links(lbm_ctx *h)
+{
+    void *p[] = {h->wl_node, h->wl_blk, h->wl_wblk, h->wl_part};
+    for (void *q : p)
+        if (q) (void)hipFree(q);
+    h->wl_node = nullptr;
+    h->wl_blk = h->wl_wblk = nullptr;
+    h->wl_part = nullptr;
+    h->n_wblk = 0;
+    h->device_bytes -= h->wl_bytes;
+    h->wl_bytes = 0;
+}
+
+// List the wall links of a wall map (host array, ids 1..n_walls, 0 = none):
+// every fluid-side node x with the wall voxel x - c_I, grouped by wall and
+// direction I, cut into chunks of kWallChunk links.
+lbm_status build_wall_links(lbm_ctx *h, const uint8_t *wall, int n_walls)
+{
+    if (n_walls < 0 || n_walls > h->cfg.max_walls) return fail(h, LBM_ERR_ARG, "n_walls %d out of range", n_walls);
+    for (int n = 0; n < h->N; ++n)
+        if (wall[n] > n_walls) return fail(h, LBM_ERR_ARG, "wall id %d at node %d exceeds n_walls", wall[n], n);
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    free_wall_links(h);
+    const int nx = h->cfg.nx, ny = h->cfg.ny, nz = h->cfg.nz;
+    std::vector<std::vector<uint32_t>> seg((size_t)n_walls * (kQ - 1));
+    if (n_walls > 0) {
+        auto wrap = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const size_t n = (size_t)x + (size_t)nx * (y + (size_t)ny * z);
+                    if (wall[n]) continue;
+                    for (int i = 1; i < kQ; ++i) {
+                        const size_t s = (size_t)wrap(x - dev::CX[i], nx) +
+                                         (size_t)nx * (wrap(y - dev::CY[i], ny) + (size_t)ny * wrap(z - dev::CZ[i], nz));
+                        const int w = wall[s];
+                        if (w) seg[(size_t)(w - 1) * (kQ - 1) + (i - 1)].push_back((uint32_t)n);
+                    }
+                }
+    }
+    std::vector<uint32_t> nodes;
+    std::vector<int> blk, wblk(1, 0);
+    for (int w = 0; w < n_walls; ++w) {
+        for (int i = 1; i < kQ; ++i) {
+            const int sg = w * (kQ - 1) + (i - 1);
+            const std::vector<uint32_t> &v = seg[sg];
+            for (size_t c = 0; c < v.size(); c += kWallChunk) {
+                blk.push_back(sg);
+                blk.push_back((int)(nodes.size() + c));
+                blk.push_back((int)(nodes.size() + std::min(v.size(), c + kWallChunk)));
+            }
+            nodes.insert(nodes.end(), v.begin(), v.end());
+        }
+        wblk.push_back((int)(blk.size() / 3));
+    }
+    h->n_wblk = (int)(blk.size() / 3);
+    const int64_t before = h->device_bytes;
+    HIP_TRY(h, dalloc(h, &h->wl_node, sizeof(uint32_t) * nodes.size()));
+    HIP_TRY(h, dalloc(h, &h->wl_blk, sizeof(int) * blk.size()));
+    HIP_TRY(h, dalloc(h, &h->wl_wblk, sizeof(int) * wblk.size()));
+    HIP_TRY(h, dalloc(h, &h->wl_part, sizeof(double) * 6 * (size_t)h->n_wblk));
+    h->wl_bytes = h->device_bytes - before;
+    TRY(copy_sync(h, h->wl_node, nodes.data(), sizeof(uint32_t) * nodes.size(), hipMemcpyHostToDevice));
+    TRY(copy_sync(h, h->wl_blk, blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice));
+    TRY(copy_sync(h, h->wl_wblk, wblk.data(), sizeof(int) * wblk.size(), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
 
 }  // namespace
 
@@ -220,17 +286,11 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
     h->n_tiles = h->ntx * h->nty * h->ntz;
     if (dalloc(h, &h->pop[0], popb) != hipSuccess || dalloc(h, &h->pop[1], popb) != hipSuccess ||
         dalloc(h, &h->own, sizeof(uint16_t) * N + 4) != hipSuccess ||
-        dalloc(h, &h->nmask, sizeof(uint32_t) * N) != hipSuccess ||
         dalloc(h, &h->wall_map, (size_t)N) != hipSuccess ||
         dalloc(h, &h->tab[0], sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->tab[1], sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->walls, sizeof(double) * kWallStride * std::max(c.max_walls, 1)) != hipSuccess ||
         dalloc(h, &h->acc, sizeof(double) * 6 * std::max(nbt, 1)) != hipSuccess ||
-        dalloc(h, &h->rec_n, sizeof(int) * (size_t)h->n_tiles) != hipSuccess ||
-        dalloc(h, &h->rec_id, sizeof(int) * (size_t)h->n_tiles * kRec) != hipSuccess ||
-        dalloc(h, &h->rec_v, sizeof(double) * 6 * (size_t)h->n_tiles * kRec) != hipSuccess ||
-        dalloc(h, &h->wallpart, sizeof(double) * 6 * (size_t)h->n_tiles * std::max(c.max_walls, 1)) != hipSuccess ||
-        dalloc(h, &h->overflow, sizeof(double) * 6 * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->flag, sizeof(int)) != hipSuccess)
         return bail(LBM_ERR_OOM);
     if (hipHostMalloc((void **)&h->pinned, sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
@@ -241,7 +301,6 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         hipMemsetAsync(h->pop[0], 0, popb, h->stream) != hipSuccess ||
         hipMemsetAsync(h->pop[1], 0, popb, h->stream) != hipSuccess ||
         hipMemsetAsync(h->acc, 0, sizeof(double) * 6 * std::max(nbt, 1), h->stream) != hipSuccess ||
-        hipMemsetAsync(h->overflow, 0, sizeof(double) * 6 * std::max(c.max_bodies, 1), h->stream) != hipSuccess ||
         hipMemsetAsync(h->flag, 0, sizeof(int), h->stream) != hipSuccess)
         return bail(LBM_ERR_HIP);
     if (rasterize_full(h) != LBM_OK) return bail(LBM_ERR_HIP);
@@ -258,9 +317,9 @@ void lbm_destroy(lbm_handle h)
         (void)hipEventDestroy(p.first);
         (void)hipEventDestroy(p.second);
     }
-    void *dev[] = {h->pop[0], h->pop[1], h->own, h->nmask, h->wall_map, h->tab[0], h->tab[1],
-                   h->walls, h->acc, h->flag, h->scratch, h->rec_n, h->rec_id, h->rec_v,
-                   h->wallpart, h->overflow};
+    free_wall_links(h);
+    void *dev[] = {h->pop[0], h->pop[1], h->own, h->wall_map, h->tab[0], h->tab[1],
+                   h->walls, h->acc, h->flag, h->scratch};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (h->pinned) (void)hipHostFree(h->pinned);
@@ -300,6 +359,7 @@ lbm_status lbm_set_walls(lbm_handle h, const uint8_t *wall_id, int32_t n_walls, 
         }
     TRY(copy_sync(h, h->wall_map, wall_id, (size_t)h->N, hipMemcpyHostToDevice));
     TRY(copy_sync(h, h->walls, wt.data(), sizeof(double) * wt.size(), hipMemcpyHostToDevice));
+    TRY(build_wall_links(h, wall_id, n_walls));
     h->n_walls = n_walls;
     return rasterize_full(h);
 }
@@ -417,22 +477,31 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
     a.fx = (float)c.body_force[0];
     a.fy = (float)c.body_force[1];
     a.fz = (float)c.body_force[2];
-    a.halfway = c.bb_mode == LBM_BB_HALFWAY;
     a.own = h->own;
-    a.nmask = h->nmask;
-    a.walls = h->walls;
-    a.rec_n = h->rec_n;
-    a.rec_id = h->rec_id;
-    a.rec_v = h->rec_v;
-    a.wallpart = h->wallpart;
-    a.overflow = h->overflow;
-    a.out = h->acc;
     a.flag = c.nan_guard_every > 0 ? h->flag : nullptr;
+    LinkArgs la{};
+    la.nx = c.nx;
+    la.ny = c.ny;
+    la.nz = c.nz;
+    la.Ns = h->Ns;
+    la.halfway = c.bb_mode == LBM_BB_HALFWAY;
+    la.rho0 = (float)c.rho0;
+    la.own = h->own;
+    la.walls = h->walls;
+    la.wl_node = h->wl_node;
+    la.wl_blk = h->wl_blk;
+    la.wl_wblk = h->wl_wblk;
+    la.wl_part = h->wl_part;
+    la.out = h->acc;
     for (int s = 0; s < nsteps; ++s) {
         if (h->dirty && (st = rasterize_update(h)) != LBM_OK) return st;
-        a.n_walls = h->n_walls;
-        a.nb = h->nb_state;
-        a.bodies = h->tab[h->ts];
+        la.n_walls = h->n_walls;
+        la.n_wblk = h->n_walls > 0 ? h->n_wblk : 0;
+        la.nb = h->nb_state;
+        la.bodies = h->tab[h->ts];
+        la.pop = h->pop[h->cur];
+        HIP_TRY(h, launch_links(c.storage, la, h->stream));
+        HIP_TRY(h, launch_wall_forces(la, h->stream));
         a.src = h->pop[h->cur];
         a.dst = h->pop[1 - h->cur];
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -446,7 +515,6 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
             HIP_TRY(h, hipEventRecord(e1, h->stream));
             h->prof_ev.emplace_back(e0, e1);
         }
-        HIP_TRY(h, launch_forces(a, h->stream));
         h->cur = 1 - h->cur;
         h->steps_done++;
         if (c.nan_guard_every > 0 && (h->steps_done % c.nan_guard_every == 0 || s == nsteps - 1)) {
@@ -626,6 +694,7 @@ lbm_status lbm_set_state(lbm_handle h, const void *buf, size_t bytes)
     TRY(copy_sync(h, h->own, p, sizeof(uint16_t) * h->N, hipMemcpyHostToDevice));
     p += sizeof(uint16_t) * h->N;
     TRY(copy_sync(h, h->wall_map, p, (size_t)h->N, hipMemcpyHostToDevice));
+    TRY(build_wall_links(h, reinterpret_cast<const uint8_t *>(p), hd.n_walls));
     p += h->N;
     TRY(copy_sync(h, h->tab[h->ts], p, tabb, hipMemcpyHostToDevice));
     p += tabb;

@@ -107,6 +107,38 @@ __device__ __forceinline__ double eq_dev(int i, double rho0, double u0, double u
     return wgt(i) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * (u0 * u0 + u1 * u1 + u2 * u2));
 }
 
+// |p - X|^2 with the minimum image, as a plain product-sum evaluated left to
+// right without fused multiply-add (the owner test compares it with R^2).
+__device__ __forceinline__ double dist2(const double *B, int px, int py, int pz, int nx, int ny, int nz)
+{
+    const double dx = min_image((double)px - B[0], nx);
+    const double dy = min_image((double)py - B[1], ny);
+    const double dz = min_image((double)pz - B[2], nz);
+    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+__device__ __forceinline__ bool inside(const double *B, int px, int py, int pz, int nx, int ny, int nz)
+{
+    return dist2(B, px, py, pz, nx, ny, nz) <= __dmul_rn(B[9], B[9]);
+}
+
+// Integer box holding every node of a sphere (grown by `pad` nodes).
+struct Box {
+    int x0, y0, z0, ex, ey, ez;
+};
+
+__device__ __forceinline__ Box body_box(const double *B, int pad)
+{
+    Box b;
+    b.x0 = (int)ceil(B[0] - B[9]) - pad;
+    b.y0 = (int)ceil(B[1] - B[9]) - pad;
+    b.z0 = (int)ceil(B[2] - B[9]) - pad;
+    b.ex = (int)floor(B[0] + B[9]) + pad - b.x0 + 1;
+    b.ey = (int)floor(B[1] + B[9]) + pad - b.y0 + 1;
+    b.ez = (int)floor(B[2] + B[9]) + pad - b.z0 + 1;
+    return b;
+}
+
 // Rigid-body velocity V + Omega x r at node p, r the minimum image of p - X.
 __device__ __forceinline__ void sphere_velocity(const double *B, int px, int py, int pz, int nx, int ny, int nz,
                                                 double &u0, double &u1, double &u2)

@@ -3,10 +3,9 @@
 // The owner map is kept incrementally when spheres move: vacate the previous
 // geometry's sphere nodes (tagging them kVacated | id), stamp the new
 // spheres with an atomic minimum (walls and lower sphere indices win), then
-// settle the neighbourhood of every old and new sphere: a node still tagged
-// kVacated was uncovered and is refilled with the equilibrium at rho0 and the
-// velocity it had as a solid (the solid-side Maxwell equilibrium of Sec. 2.3),
-// and every fluid node there gets its near-boundary flag recomputed.  One
+// settle every old sphere's box: a node still tagged kVacated | id was
+// uncovered and is refilled with the equilibrium at rho0 and the velocity it
+// had as a solid (the solid-side Maxwell equilibrium of Sec. 2.3).  One
 // workgroup per sphere walks the sphere's bounding box with an 8x8x4 thread
 // block.
 #include "lbm_device.h"
@@ -21,33 +20,6 @@ namespace lbm {
 namespace {
 
 using namespace dev;
-
-// |p - X|^2 <= R^2 with the minimum image, as a plain product-sum evaluated
-// left to right without fused multiply-add.
-__device__ __forceinline__ bool inside(const double *B, int px, int py, int pz, int nx, int ny, int nz)
-{
-    const double dx = min_image((double)px - B[0], nx);
-    const double dy = min_image((double)py - B[1], ny);
-    const double dz = min_image((double)pz - B[2], nz);
-    const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-    return d2 <= __dmul_rn(B[9], B[9]);
-}
-
-struct Box {
-    int x0, y0, z0, ex, ey, ez;
-};
-
-__device__ __forceinline__ Box body_box(const double *B, int pad)
-{
-    Box b;
-    b.x0 = (int)ceil(B[0] - B[9]) - pad;
-    b.y0 = (int)ceil(B[1] - B[9]) - pad;
-    b.z0 = (int)ceil(B[2] - B[9]) - pad;
-    b.ex = (int)floor(B[0] + B[9]) + pad - b.x0 + 1;
-    b.ey = (int)floor(B[1] + B[9]) + pad - b.y0 + 1;
-    b.ez = (int)floor(B[2] + B[9]) + pad - b.z0 + 1;
-    return b;
-}
 
 // Visit every node of a body's box with a (8, 8, 4) workgroup.
 template <typename F>
@@ -80,36 +52,10 @@ __device__ __forceinline__ void atomic_min_u16(uint16_t *addr, uint16_t val)
     }
 }
 
-// Solid-link mask of a fluid node: bit i set when the pull source x - c_i
-// is solid (kVacated nodes count as fluid: they are about to be refilled).
-__device__ __forceinline__ uint32_t link_mask(const uint16_t *own, int x, int y, int z, int nx, int ny, int nz)
-{
-    uint32_t m = 0;
-#pragma unroll
-    for (int i = 1; i < kQ; ++i) {
-        const int s = wrap_add(x, -CX[i], nx) + nx * (wrap_add(y, -CY[i], ny) + ny * wrap_add(z, -CZ[i], nz));
-        if (own[s] < kVacated) m |= 1u << i;
-    }
-    return m;
-}
-
 __global__ __launch_bounds__(kBlock) void k_walls_init(const uint8_t *wall, uint16_t *own, int N)
 {
     const int n = blockIdx.x * kBlock + threadIdx.x;
     if (n < N) own[n] = wall[n] ? (uint16_t)(wall[n] - 1) : kFluid;
-}
-
-__global__ __launch_bounds__(kBlock) void k_flags_full(GeomArgs g)
-{
-    const int n = blockIdx.x * kBlock + threadIdx.x;
-    if (n >= g.N) return;
-    const uint16_t o = g.own[n];
-    if (o < kNear) return;
-    const int x = n % g.nx, y = (n / g.nx) % g.ny, z = n / (g.nx * g.ny);
-    const uint32_t m = link_mask(g.own, x, y, z, g.nx, g.ny, g.nz);
-    g.nmask[n] = m;
-    const uint16_t f = m ? kNear : kFluid;
-    if (f != o) g.own[n] = f;
 }
 
 __global__ __launch_bounds__(kBlock) void k_vacate(GeomArgs g)
@@ -135,35 +81,24 @@ __global__ __launch_bounds__(kBlock) void k_stamp(GeomArgs g)
     });
 }
 
-// Refill uncovered nodes and refresh near flags around old (blocks < nb)
-// and new (blocks >= nb) spheres.
+// Refill the nodes the old sphere `blockIdx.x` uncovered: the equilibrium at
+// rho0 and the velocity the node had as a solid; they become fluid.
 template <int S>
 __global__ __launch_bounds__(kBlock) void k_settle(GeomArgs g)
 {
     using St = Store<S>;
     typename St::T *pop = static_cast<typename St::T *>(g.pop);
-    const int j = blockIdx.x;
-    const double *B = j < g.nb ? g.bodies + j * kBodyStride : g.bodies2 + (j - g.nb) * kBodyStride;
+    const double *B = g.bodies + blockIdx.x * kBodyStride;
     if (!body_ok(B, g.nx, g.ny, g.nz)) return;
+    const uint16_t tag = (uint16_t)(kVacated | (g.n_walls + blockIdx.x));
     uint16_t *own = g.own;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
-    for_box(body_box(B, 1), nx, ny, nz, [&](int px, int py, int pz, int n) {
-        const uint16_t o = own[n];
-        if (o >= kNear) {
-            const uint32_t msk = link_mask(own, px, py, pz, nx, ny, nz);
-            g.nmask[n] = msk;
-            const uint16_t f = msk ? kNear : kFluid;
-            if (f != o) own[n] = f;
-        } else if (o & kVacated) {
-            // uncovered: equilibrium at rho0 and the old solid velocity
-            const double *Bo = g.bodies + ((o & 0x7fff) - g.n_walls) * kBodyStride;
-            double u0, u1, u2;
-            sphere_velocity(Bo, px, py, pz, nx, ny, nz, u0, u1, u2);
-            for (int i = 0; i < kQ; ++i) St::st(pop + (size_t)i * g.Ns + n, (float)eq_dev(i, g.rho0, u0, u1, u2));
-            const uint32_t msk = link_mask(own, px, py, pz, nx, ny, nz);
-            g.nmask[n] = msk;
-            own[n] = msk ? kNear : kFluid;
-        }
+    for_box(body_box(B, 0), nx, ny, nz, [&](int px, int py, int pz, int n) {
+        if (own[n] != tag) return;
+        double u0, u1, u2;
+        sphere_velocity(B, px, py, pz, nx, ny, nz, u0, u1, u2);
+        for (int i = 0; i < kQ; ++i) St::st(pop + (size_t)i * g.Ns + n, (float)eq_dev(i, g.rho0, u0, u1, u2));
+        own[n] = kFluid;
     });
 }
 
@@ -175,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_init_pop(GeomArgs g, const double *r
     const int n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
     const size_t N = (size_t)g.N;
-    if (g.own[n] < kNear) {
+    if (g.own[n] < kVacated) {
         for (int i = 0; i < kQ; ++i) St::st(pop + i * (size_t)g.Ns + n, 0.0f);
         return;
     }
@@ -209,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_export_pop(GeomArgs g, const double 
     const int n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
     const uint16_t o = g.own[n];
-    if (o >= kNear) {
+    if (o >= kVacated) {
         out[n] = (double)St::ld(pop + (size_t)dir * g.Ns + n) + wgt(dir) * (double)g.rho0;
         return;
     }
@@ -238,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_export_macro(GeomArgs g, const doubl
     if (n >= g.N) return;
     const size_t N = (size_t)g.N;
     const uint16_t o = g.own[n];
-    if (o >= kNear) {
+    if (o >= kVacated) {
         double r = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
         for (int i = 0; i < kQ; ++i) {
             const double f = (double)St::ld(pop + i * (size_t)g.Ns + n) + wgt(i) * (double)g.rho0;
@@ -265,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_export_macro(GeomArgs g, const doubl
 __global__ __launch_bounds__(kBlock) void k_export_owner(const uint16_t *own, int N, int32_t *out)
 {
     const int n = blockIdx.x * kBlock + threadIdx.x;
-    if (n < N) out[n] = own[n] >= kNear ? -1 : (int32_t)own[n];
+    if (n < N) out[n] = own[n] >= kVacated ? -1 : (int32_t)own[n];
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero(double *p, int n)
@@ -280,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_count_fluid(const uint16_t *own, int
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
     unsigned int c = 0;
-    for (int n = blockIdx.x * kBlock + threadIdx.x; n < N; n += gridDim.x * kBlock) c += own[n] >= kNear;
+    for (int n = blockIdx.x * kBlock + threadIdx.x; n < N; n += gridDim.x * kBlock) c += own[n] >= kVacated;
     atomicAdd(&s_cnt, c);
     __syncthreads();
     if (threadIdx.x == 0 && s_cnt) atomicAdd(count, (unsigned long long)s_cnt);
@@ -315,12 +250,6 @@ hipError_t launch_walls_init(const uint8_t *wall, uint16_t *own, int N, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_flags_full(const GeomArgs &g, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_flags_full, dim3(nblk(g.N)), dim3(kBlock), 0, s, g);
-    return hipGetLastError();
-}
-
 hipError_t launch_vacate(const GeomArgs &g, hipStream_t s)
 {
     if (g.nb <= 0) return hipSuccess;
@@ -337,8 +266,8 @@ hipError_t launch_stamp(const GeomArgs &g, hipStream_t s)
 
 hipError_t launch_settle(int storage, const GeomArgs &g, hipStream_t s)
 {
-    if (g.nb + g.nb2 <= 0) return hipSuccess;
-    return dispatch<SettleK>(storage, dim3(g.nb + g.nb2), kBoxBlock, s, g);
+    if (g.nb <= 0) return hipSuccess;
+    return dispatch<SettleK>(storage, dim3(g.nb), kBoxBlock, s, g);
 }
 
 hipError_t launch_init_pop(int storage, const GeomArgs &g, const double *rho, const double *u, hipStream_t s)

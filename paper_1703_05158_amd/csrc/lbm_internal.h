@@ -1,5 +1,6 @@
 // Internal interface between the C-ABI host layer (lbm_api.cpp) and the
-// gfx950 kernels (lbm_step.hip, lbm_geometry.hip).  Not part of the ABI.
+// gfx950 kernels (lbm_step.hip, lbm_links.hip, lbm_geometry.hip).  Not part
+// of the ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,24 +13,23 @@ constexpr int kQ = 19;
 // Owner map codes (uint16 per node).  Solid owners are ids below kVacated:
 // walls 0..n_walls-1, then spheres n_walls + b.  kVacated | id marks a node
 // that the previous geometry's sphere `id` covered while the map is being
-// rebuilt.  kNear marks fluid nodes with at least one solid neighbour among
-// the 18 links; kFluid marks the remaining fluid nodes.  For kNear nodes a
-// separate uint32 per node holds the solid-link mask: bit i set when the
-// pull source x - c_i is solid.
+// rebuilt (it counts as fluid); kFluid marks the fluid nodes.
 constexpr uint16_t kFluid = 0xFFFF;
-constexpr uint16_t kNear = 0xFFFE;
 constexpr uint16_t kVacated = 0x8000;
 constexpr int kMaxIds = 0x7FFE;
 
 constexpr int kBodyStride = 10;   // X[3], V[3], Omega[3], R
 constexpr int kWallStride = 6;    // U[3], ref[3]
-constexpr int kMaxWalls = 16;     // walls get dedicated per-tile force slots
-constexpr int kRec = 32;          // per-tile force records of spheres
-constexpr int kBlock = 256;       // threads of a step workgroup (one tile)
+constexpr int kMaxWalls = 16;
+constexpr int kBlock = 256;       // threads of a workgroup
+constexpr int kWallChunk = 1024;  // wall links per workgroup of the link pass
 
 // Tile shapes of the step kernel (x extent; y and z fill 256 threads).
 enum TileShape { kTile64x2x2 = 0, kTile32x4x2 = 1 };
 
+// Pull-collide step over the fluid nodes.  The populations pulled across a
+// cut link come from the solid node's slot, where the link pass has put the
+// bounce-back value.
 struct StepArgs {
     int nx, ny, nz, N;
     int Ns;                       // stride between direction arrays (elements, >= N)
@@ -37,20 +37,30 @@ struct StepArgs {
     int ntx, nty, ntz, n_tiles;
     float tau0, smag_k, rho0;     // smag_k = 18 sqrt(2) C^2
     float fx, fy, fz;
-    int n_walls, nb, halfway;
     const uint16_t *own;
-    const uint32_t *nmask;        // solid-link mask of near-boundary nodes
     const void *src;
     void *dst;
-    const double *bodies;
-    const double *walls;
-    int *rec_n;                   // [n_tiles]
-    int *rec_id;                  // [n_tiles][kRec]
-    double *rec_v;                // [n_tiles][kRec][6]
-    double *wallpart;             // [n_tiles][n_walls][6]
-    double *overflow;             // [max_bodies][6], zero between steps
-    double *out;                  // [nb + n_walls][6]
-    int *flag;
+    int *flag;                    // NaN guard, may be null
+};
+
+// Boundary-link pass: for every link from a fluid node x to a solid node
+// x + c_K, the value of the population I = opposite(K) that x receives is
+// written to slot I of the solid node, and the momentum exchanged on the
+// link is reduced per body.
+struct LinkArgs {
+    int nx, ny, nz, Ns;
+    int n_walls, nb, halfway;
+    float rho0;
+    const uint16_t *own;
+    void *pop;                    // current state: read at fluid nodes, written at solid nodes
+    const double *bodies;         // [nb][kBodyStride]
+    const double *walls;          // [n_walls][kWallStride]
+    const uint32_t *wl_node;      // fluid nodes of the wall links, grouped by (wall, direction)
+    const int *wl_blk;            // [n_wblk][3]: segment w * 18 + I - 1, begin, end
+    int n_wblk;
+    double *wl_part;              // [n_wblk][6]
+    const int *wl_wblk;           // [n_walls + 1]: each wall's range of workgroups
+    double *out;                  // [nb + n_walls][6]: F, T
 };
 
 struct GeomArgs {
@@ -60,20 +70,17 @@ struct GeomArgs {
     int n_walls;
     const double *bodies;
     int nb;
-    const double *bodies2;        // new geometry's table (settle pass)
-    int nb2;
     uint16_t *own;
-    uint32_t *nmask;
     void *pop;
     float rho0;
 };
 
 // storage: 0 = fp32, 1 = fp16, 2 = bf16 deviations
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t s);
-hipError_t launch_forces(const StepArgs &a, hipStream_t s);
+hipError_t launch_links(int storage, const LinkArgs &a, hipStream_t s);
+hipError_t launch_wall_forces(const LinkArgs &a, hipStream_t s);
 
 hipError_t launch_walls_init(const uint8_t *wall, uint16_t *own, int N, hipStream_t s);
-hipError_t launch_flags_full(const GeomArgs &g, hipStream_t s);
 hipError_t launch_vacate(const GeomArgs &g, hipStream_t s);
 hipError_t launch_stamp(const GeomArgs &g, hipStream_t s);
 hipError_t launch_settle(int storage, const GeomArgs &g, hipStream_t s);
