@@ -130,7 +130,10 @@ lbm_status rasterize_update(lbm_ctx *h)
     GeomArgs new_g = old_g;
     new_g.bodies = h->tab[1 - h->ts];
     new_g.nb = h->nb_next;
-    HIP_TRY(h, launch_vacate(old_g, h->stream));
+    GeomArgs vac = old_g;
+    vac.bodies2 = new_g.bodies;
+    vac.nb2 = new_g.nb;
+    HIP_TRY(h, launch_vacate(vac, h->stream));
     HIP_TRY(h, launch_stamp(new_g, h->stream));
     HIP_TRY(h, launch_settle(h->cfg.storage, old_g, h->stream));
     h->ts = 1 - h->ts;

@@ -1,8 +1,9 @@
 // Owner-map maintenance and state import/export kernels (gfx950).
 //
-// The owner map is kept incrementally when spheres move: vacate the previous
-// geometry's sphere nodes (tagging them kVacated | id), stamp the new
-// spheres with an atomic minimum (walls and lower sphere indices win), then
+// The owner map is kept incrementally when spheres move: vacate the nodes a
+// sphere owned in the previous geometry and no longer covers (tagging them
+// kVacated | id), stamp the new spheres with an atomic minimum (walls and
+// lower sphere indices win; nodes a sphere keeps need no atomic), then
 // settle every old sphere's box: a node still tagged kVacated | id was
 // uncovered and is refilled with the equilibrium at rho0 and the velocity it
 // had as a solid (the solid-side Maxwell equilibrium of Sec. 2.3).  One
@@ -58,14 +59,19 @@ __global__ __launch_bounds__(kBlock) void k_walls_init(const uint8_t *wall, uint
     if (n < N) own[n] = wall[n] ? (uint16_t)(wall[n] - 1) : kFluid;
 }
 
+// Old sphere blockIdx.x against its new position (g.bodies2, g.nb2 spheres).
 __global__ __launch_bounds__(kBlock) void k_vacate(GeomArgs g)
 {
-    const double *B = g.bodies + blockIdx.x * kBodyStride;
+    const int b = blockIdx.x;
+    const double *B = g.bodies + b * kBodyStride;
     if (!body_ok(B, g.nx, g.ny, g.nz)) return;
-    const uint16_t id = (uint16_t)(g.n_walls + blockIdx.x);
+    const double *Bn = g.bodies2 + b * kBodyStride;
+    const bool keeps = b < g.nb2 && body_ok(Bn, g.nx, g.ny, g.nz);
+    const uint16_t id = (uint16_t)(g.n_walls + b);
     uint16_t *own = g.own;
-    for_box(body_box(B, 0), g.nx, g.ny, g.nz, [&](int, int, int, int n) {
-        if (own[n] == id) own[n] = (uint16_t)(kVacated | id);
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    for_box(body_box(B, 0), nx, ny, nz, [&](int px, int py, int pz, int n) {
+        if (own[n] == id && !(keeps && inside(Bn, px, py, pz, nx, ny, nz))) own[n] = (uint16_t)(kVacated | id);
     });
 }
 

@@ -70,6 +70,8 @@ struct GeomArgs {
     int n_walls;
     const double *bodies;
     int nb;
+    const double *bodies2;        // vacate: the new geometry's table
+    int nb2;
     uint16_t *own;
     void *pop;
     float rho0;

@@ -12,8 +12,8 @@
 //  - one workgroup per sphere walks the sphere's box and lists candidate
 //    links from the geometry alone (FP32 distances with a margin, no memory
 //    access), spreads them evenly over its threads, confirms each with the
-//    owner map (loads issued together with the population loads, so a link
-//    costs one memory round trip) and reduces force and torque itself;
+//    owner map (loads issued together with the population loads, two links
+//    per thread in flight) and reduces force and torque itself;
 //  - wall links do not change while the walls stay: their fluid nodes are
 //    listed once per (wall, direction); workgroups take chunks of the list
 //    and write per-chunk sums that k_wall_forces adds up per wall.
@@ -53,67 +53,104 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*s_red)[6])
         }
 }
 
-// Candidate link from the fluid node x = p + c_I to the node p of sphere B
-// (owner code ob): a link when p belongs to the sphere and x is fluid.
+// Sphere kinematics of one workgroup: centre (FP64), the rest in FP32.
+struct SphereK {
+    double X0, X1, X2;
+    float V0, V1, V2, W0, W1, W2, R2;
+};
+
+// Candidate link (p, I) from the fluid node x = p + c_I to the node p of a
+// sphere.  The geometry comes first (it needs no memory): q decides which
+// second population the interpolation uses, so a link loads the owner codes
+// of p, x (and of the node behind x when q < 1/2) and two populations, all in
+// one round trip.  Populations read at a node that turns out to be solid are
+// discarded (the load may see a link value being written there).
+struct LinkLoad {
+    int I;
+    uint32_t pi;
+    uint16_t op, ox, ob;
+    float fk, f2;         // f2: P(x)[I] when q >= 1/2, else P(x - c_K)[K]
+    float q, mw;          // Bouzidi q and the moving-boundary term
+    double d0, d1, d2;    // x - X (minimum image)
+};
+
 template <int S>
-__device__ __forceinline__ void sphere_link(const LinkArgs &a, typename Store<S>::T *pop, const double *B,
-                                            uint16_t ob, int px, int py, int pz, int I, double (&acc)[6])
+__device__ __forceinline__ LinkLoad link_load(const LinkArgs &a, const typename Store<S>::T *pop,
+                                              const SphereK &k, int px, int py, int pz, int I)
 {
     using St = Store<S>;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t Ns = (size_t)a.Ns;
-    const int K = opp(I);
     const int cx = dcx(I), cy = dcy(I), cz = dcz(I);  // c_I = -c_K
+    const int K = opp(I);
+    LinkLoad l;
+    l.I = I;
     const int x = wrap1(px + cx, nx), y = wrap1(py + cy, ny), z = wrap1(pz + cz, nz);
-    const uint32_t pi = (uint32_t)(px + nx * (py + ny * pz));
+    l.pi = (uint32_t)(px + nx * (py + ny * pz));
     const uint32_t xi = (uint32_t)(x + nx * (y + ny * z));
-    const uint32_t bi = (uint32_t)(wrap1(x + cx, nx) + nx * (wrap1(y + cy, ny) + ny * wrap1(z + cz, nz)));
-    // All issued together.  Populations read at a node that turns out to be
-    // solid are discarded (the load may see a link value being written there).
-    const uint16_t op = *at(a.own, pi), ox = *at(a.own, xi), obk = *at(a.own, bi);
-    const float fk = St::ld(at(pop + (size_t)K * Ns, xi));
-    const float fi = St::ld(at(pop + (size_t)I * Ns, xi));
-    const float gb = St::ld(at(pop + (size_t)K * Ns, bi));
-    if (op != ob || ox < kVacated) return;
-    const bool back_fluid = obk >= kVacated;
-
-    const double ckx = -cx, cky = -cy, ckz = -cz;
-    const double d0 = min_image((double)x - B[0], nx);
-    const double d1 = min_image((double)y - B[1], ny);
-    const double d2 = min_image((double)z - B[2], nz);
-    double q;
+    // geometry: distance from the centre in FP64, rounded once; q and the
+    // wall velocity in FP32
+    l.d0 = min_image((double)x - k.X0, nx);
+    l.d1 = min_image((double)y - k.X1, ny);
+    l.d2 = min_image((double)z - k.X2, nz);
+    const float e0 = (float)l.d0, e1 = (float)l.d1, e2 = (float)l.d2;
     if (a.halfway) {
-        q = 0.5;
+        l.q = 0.5f;
     } else {
         // smallest root in (0,1] of |d + q c_K|^2 = R^2, cancellation-free form
-        const double bb = d0 * ckx + d1 * cky + d2 * ckz;
-        const double aa = (double)(cx * cx + cy * cy + cz * cz);
-        const double cc = __dadd_rn(__dadd_rn(__dmul_rn(d0, d0), __dmul_rn(d1, d1)), __dmul_rn(d2, d2)) -
-                          __dmul_rn(B[9], B[9]);
-        const double disc = fmax(bb * bb - aa * cc, 0.0);
-        q = fmin(fmax(cc / (sqrt(disc) - bb), 0.0), 1.0);
+        const float bb = -(e0 * cx + e1 * cy + e2 * cz);
+        const float aa = (float)(cx * cx + cy * cy + cz * cz);
+        const float cc = (e0 * e0 + e1 * e1 + e2 * e2) - k.R2;
+        const float disc = fmaxf(bb * bb - aa * cc, 0.0f);
+        l.q = fminf(fmaxf(cc / (__builtin_sqrtf(disc) - bb), 0.0f), 1.0f);
     }
     // wall point x_b = x + q c_K relative to the centre, and its velocity
-    const double ar0 = d0 + q * ckx, ar1 = d1 + q * cky, ar2 = d2 + q * ckz;
-    const double u0 = B[3] + (B[7] * ar2 - B[8] * ar1);
-    const double u1 = B[4] + (B[8] * ar0 - B[6] * ar2);
-    const double u2 = B[5] + (B[6] * ar1 - B[7] * ar0);
+    const float f0 = e0 - l.q * cx, f1 = e1 - l.q * cy, f2 = e2 - l.q * cz;
+    const float u0 = k.V0 + (k.W1 * f2 - k.W2 * f1);
+    const float u1 = k.V1 + (k.W2 * f0 - k.W0 * f2);
+    const float u2 = k.V2 + (k.W0 * f1 - k.W1 * f0);
     // moving-boundary term along the reflected direction I
-    const float wk = (float)wgt(K);
-    const float mw = wk * a.rho0 * (float)(cx * u0 + cy * u1 + cz * u2);
-    const float qf = (float)q;
-    float val;
-    if (q < 0.5) {
-        val = back_fluid ? 2.0f * qf * fk + (1.0f - 2.0f * qf) * gb + 6.0f * mw : fk + 6.0f * mw;
+    l.mw = (float)wgt(K) * a.rho0 * (cx * u0 + cy * u1 + cz * u2);
+    l.op = *at(a.own, l.pi);
+    l.ox = *at(a.own, xi);
+    l.fk = St::ld(at(pop + (size_t)K * Ns, xi));
+    if (l.q < 0.5f) {
+        const uint32_t bi = (uint32_t)(wrap1(x + cx, nx) + nx * (wrap1(y + cy, ny) + ny * wrap1(z + cz, nz)));
+        l.ob = *at(a.own, bi);
+        l.f2 = St::ld(at(pop + (size_t)K * Ns, bi));
     } else {
-        const float h = 0.5f / qf;
-        val = h * fk + (1.0f - h) * fi + (3.0f / qf) * mw;
+        l.ob = kFluid;
+        l.f2 = St::ld(at(pop + (size_t)I * Ns, xi));
+    }
+    return l;
+}
+
+// The link, if it is one (p owned by the sphere `own_b`, x fluid): the
+// Bouzidi value into slot I of p and the momentum into acc (lever arm and
+// sums in FP64).
+template <int S>
+__device__ __forceinline__ void link_finish(const LinkArgs &a, typename Store<S>::T *pop, uint16_t own_b,
+                                            const LinkLoad &l, double (&acc)[6])
+{
+    using St = Store<S>;
+    if (l.op != own_b || l.ox < kVacated) return;
+    const int I = l.I;
+    const int cx = dcx(I), cy = dcy(I), cz = dcz(I);  // c_I = -c_K
+    const float q = l.q;
+    float val;
+    if (q < 0.5f) {
+        val = l.ob >= kVacated ? 2.0f * q * l.fk + (1.0f - 2.0f * q) * l.f2 + 6.0f * l.mw : l.fk + 6.0f * l.mw;
+    } else {
+        const float h = 0.5f / q;
+        val = h * l.fk + (1.0f - h) * l.f2 + (3.0f / q) * l.mw;
     }
     const float vr = St::round(val);
-    St::st(at(pop + (size_t)I * Ns, pi), vr);
-    // momentum handed to the body along c_K (full populations)
-    const double mom = (double)fk + (double)vr + 2.0 * (double)wk * (double)a.rho0;
-    const double F0 = mom * ckx, F1 = mom * cky, F2 = mom * ckz;
+    St::st(at(pop + (size_t)I * (size_t)a.Ns, l.pi), vr);
+    // momentum handed to the body along c_K (full populations), arm x_b - X
+    const double mom = (double)l.fk + (double)vr + 2.0 * wgt(I) * (double)a.rho0;
+    const double qd = (double)q;
+    const double ar0 = l.d0 - qd * cx, ar1 = l.d1 - qd * cy, ar2 = l.d2 - qd * cz;
+    const double F0 = -mom * cx, F1 = -mom * cy, F2 = -mom * cz;
     acc[0] += F0;
     acc[1] += F1;
     acc[2] += F2;
@@ -122,86 +159,157 @@ __device__ __forceinline__ void sphere_link(const LinkArgs &a, typename Store<S>
     acc[5] += ar0 * F1 - ar1 * F0;
 }
 
+constexpr int kItemCap = 4096;   // candidate links held at once
+constexpr int kRoundNodes = 224; // box nodes per round when a sphere has more (224 * 18 <= kItemCap)
+
 struct SphereLds {
-    uint16_t item[kBlock * (kQ - 1)];  // candidate links of one round: node slot | I << 8
-    int px[kBlock], py[kBlock], pz[kBlock];
+    uint32_t item[kItemCap];  // box node index << 5 | I
     int wtot[kWaves];
 };
 
-// Sphere b, in rounds of one box node per thread.  A node p is a candidate
-// when its FP32 distance to the centre is within a margin of the ball and
-// more than R - 1.5 (deeper nodes have no neighbour outside), and (p, I) is
-// a candidate link when p + c_I lies outside the ball by the same margin.
-// The margin covers the FP32 rounding, so every link is a candidate; the
-// owner map then decides exactly.
+// Candidate links of box node k: p is within a margin of the ball and more
+// than R - 1.5 deep at most (deeper nodes have no neighbour outside), and
+// (p, I) when p + c_I lies outside the ball by the same margin.  The margin
+// covers the FP32 rounding, so every link is a candidate; the owner map then
+// decides exactly.
+__device__ __forceinline__ uint32_t candidates(const LinkArgs &a, const Box &bx, const SphereK &k, float mg,
+                                               float in2, int kk, int &px, int &py, int &pz)
+{
+    const int kx = kk % bx.ex, kr = kk / bx.ex;
+    px = wrap1(bx.x0 + kx, a.nx);
+    py = wrap1(bx.y0 + kr % bx.ey, a.ny);
+    pz = wrap1(bx.z0 + kr / bx.ey, a.nz);
+    const float dx = (float)min_image((double)px - k.X0, a.nx);
+    const float dy = (float)min_image((double)py - k.X1, a.ny);
+    const float dz = (float)min_image((double)pz - k.X2, a.nz);
+    const float d2 = dx * dx + dy * dy + dz * dz;
+    uint32_t lm = 0;
+    if (d2 <= k.R2 + mg && d2 >= in2) {
+        // |d + c|^2 > R^2 - mg  <=>  2 d.c > R^2 - mg - d^2 - |c|^2
+        const float t = k.R2 - mg - d2;
+        const float ax = 2.0f * dx, ay = 2.0f * dy, az = 2.0f * dz;
+#pragma unroll
+        for (int i = 1; i < kQ; ++i) {
+            const float dc = CX[i] * ax + CY[i] * ay + CZ[i] * az;
+            const float cc = (float)(CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i]);
+            if (dc > t - cc) lm |= 1u << i;
+        }
+    }
+    return lm;
+}
+
+// Exclusive prefix of `cnt` over the workgroup and the total.
+__device__ __forceinline__ int block_scan(int cnt, int *wtot, int &tot)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
+    }
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    int pos = incl - cnt;
+    tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const int t = wtot[w];
+        if (w < wv) pos += t;
+        tot += t;
+    }
+    return pos;
+}
+
+// Links of the candidates listed in item[0, tot), two per thread at a time.
+template <int S>
+__device__ __forceinline__ void process_items(const LinkArgs &a, typename Store<S>::T *pop, const Box &bx,
+                                              const SphereK &k, uint16_t own_b, const uint32_t *item, int tot,
+                                              double (&acc)[6])
+{
+#pragma unroll 1
+    for (int j = threadIdx.x; j < tot; j += 2 * kBlock) {
+        const int j2 = j + kBlock;
+        int px, py, pz;
+        const uint32_t ia = item[j];
+        const int ka = (int)(ia >> 5);
+        px = wrap1(bx.x0 + ka % bx.ex, a.nx);
+        py = wrap1(bx.y0 + (ka / bx.ex) % bx.ey, a.ny);
+        pz = wrap1(bx.z0 + ka / (bx.ex * bx.ey), a.nz);
+        const LinkLoad la = link_load<S>(a, pop, k, px, py, pz, (int)(ia & 31));
+        LinkLoad lb;
+        lb.op = 0;  // no second link: fails the ownership test
+        if (j2 < tot) {
+            const uint32_t ib = item[j2];
+            const int kb = (int)(ib >> 5);
+            px = wrap1(bx.x0 + kb % bx.ex, a.nx);
+            py = wrap1(bx.y0 + (kb / bx.ex) % bx.ey, a.ny);
+            pz = wrap1(bx.z0 + kb / (bx.ex * bx.ey), a.nz);
+            lb = link_load<S>(a, pop, k, px, py, pz, (int)(ib & 31));
+        }
+        link_finish<S>(a, pop, own_b, la, acc);
+        if (j2 < tot) link_finish<S>(a, pop, own_b, lb, acc);
+    }
+}
+
+// Sphere b.  Candidates of the whole box are listed at once when they fit
+// in kItemCap, else in rounds of kRoundNodes box nodes.
 template <int S>
 __device__ __forceinline__ void sphere_block(const LinkArgs &a, int b, SphereLds &L, double (*s_red)[6])
 {
     using St = Store<S>;
     typename St::T *pop = static_cast<typename St::T *>(a.pop);
     const double *B = a.bodies + (size_t)b * kBodyStride;
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (body_ok(B, nx, ny, nz)) {
+    if (body_ok(B, a.nx, a.ny, a.nz)) {
         const Box bx = body_box(B, 0);
         const int total = bx.ex * bx.ey * bx.ez;
-        const uint16_t ob = (uint16_t)(a.n_walls + b);
-        const float R2 = (float)(B[9] * B[9]);
-        const float mg = 0.01f + 1e-5f * R2;
+        const uint16_t own_b = (uint16_t)(a.n_walls + b);
+        SphereK k;
+        k.X0 = B[0];
+        k.X1 = B[1];
+        k.X2 = B[2];
+        k.V0 = (float)B[3];
+        k.V1 = (float)B[4];
+        k.V2 = (float)B[5];
+        k.W0 = (float)B[6];
+        k.W1 = (float)B[7];
+        k.W2 = (float)B[8];
+        k.R2 = (float)(B[9] * B[9]);
+        const float mg = 0.01f + 1e-5f * k.R2;
         const float ri = (float)B[9] - 1.5f;
         const float in2 = ri > 0.0f ? ri * ri - mg : -1.0f;
-        for (int base = 0; base < total; base += kBlock) {
-            const int k = base + tid;
-            uint32_t lm = 0;
-            if (k < total) {
-                const int kx = k % bx.ex, kr = k / bx.ex;
-                const int px = wrap1(bx.x0 + kx, nx), py = wrap1(bx.y0 + kr % bx.ey, ny),
-                          pz = wrap1(bx.z0 + kr / bx.ey, nz);
-                L.px[tid] = px;
-                L.py[tid] = py;
-                L.pz[tid] = pz;
-                const float dx = (float)min_image((double)px - B[0], nx);
-                const float dy = (float)min_image((double)py - B[1], ny);
-                const float dz = (float)min_image((double)pz - B[2], nz);
-                const float d2 = dx * dx + dy * dy + dz * dz;
-                if (d2 <= R2 + mg && d2 >= in2) {
-#pragma unroll
-                    for (int i = 1; i < kQ; ++i) {
-                        const float ex = dx + CX[i], ey = dy + CY[i], ez = dz + CZ[i];
-                        if (ex * ex + ey * ey + ez * ez > R2 - mg) lm |= 1u << i;
-                    }
+        int px, py, pz, tot;
+        int cnt = 0;
+        for (int kk = tid; kk < total; kk += kBlock) cnt += __popc(candidates(a, bx, k, mg, in2, kk, px, py, pz));
+        int pos = block_scan(cnt, L.wtot, tot);
+        if (tot <= kItemCap) {
+            for (int kk = tid; kk < total; kk += kBlock) {
+                uint32_t lm = candidates(a, bx, k, mg, in2, kk, px, py, pz);
+                while (lm) {
+                    const int I = __builtin_ctz(lm);
+                    lm &= lm - 1;
+                    L.item[pos++] = ((uint32_t)kk << 5) | (uint32_t)I;
                 }
             }
-            // exclusive scan of the candidate counts over the workgroup
-            const int cnt = __popc(lm);
-            int incl = cnt;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const int v = __shfl_up(incl, off);
-                if (lane >= off) incl += v;
-            }
-            if (lane == 63) L.wtot[wv] = incl;
             __syncthreads();
-            int pos = incl - cnt, tot = 0;
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) {
-                const int t = L.wtot[w];
-                if (w < wv) pos += t;
-                tot += t;
+            process_items<S>(a, pop, bx, k, own_b, L.item, tot, acc);
+        } else {
+            for (int base = 0; base < total; base += kRoundNodes) {
+                __syncthreads();  // item and wtot of the previous pass are free
+                const int kk = base + tid;
+                uint32_t lm = 0;
+                if (tid < kRoundNodes && kk < total) lm = candidates(a, bx, k, mg, in2, kk, px, py, pz);
+                pos = block_scan(__popc(lm), L.wtot, tot);
+                while (lm) {
+                    const int I = __builtin_ctz(lm);
+                    lm &= lm - 1;
+                    L.item[pos++] = ((uint32_t)kk << 5) | (uint32_t)I;
+                }
+                __syncthreads();
+                process_items<S>(a, pop, bx, k, own_b, L.item, tot, acc);
             }
-            while (lm) {
-                const int I = __builtin_ctz(lm);
-                lm &= lm - 1;
-                L.item[pos++] = (uint16_t)(tid | (I << 8));
-            }
-            __syncthreads();
-#pragma unroll 1
-            for (int j = tid; j < tot; j += kBlock) {
-                const int it = L.item[j], sl = it & 255;
-                sphere_link<S>(a, pop, B, ob, L.px[sl], L.py[sl], L.pz[sl], it >> 8, acc);
-            }
-            __syncthreads();  // item, px/py/pz and wtot are reused by the next round
         }
     }
     block_sum<6>(acc, s_red);
@@ -280,10 +388,16 @@ __global__ __launch_bounds__(kBlock) void k_links(LinkArgs a)
 {
     __shared__ SphereLds L;
     __shared__ double s_red[kWaves][6];
-    if ((int)blockIdx.x < a.nb)
-        sphere_block<S>(a, blockIdx.x, L, s_red);
+    const int b = blockIdx.x;
+    if (b < a.nb) {
+        // workgroups go round-robin over the 8 XCDs: give each XCD a
+        // contiguous range of spheres, so that spheres that are neighbours
+        // in the table share an L2
+        const int per = a.nb >> 3;
+        sphere_block<S>(a, b >= (per << 3) ? b : (b & 7) * per + (b >> 3), L, s_red);
+    }
     else
-        wall_block<S>(a, blockIdx.x - a.nb, s_red);
+        wall_block<S>(a, b - a.nb, s_red);
 }
 
 // Wall w: the sum of its chunks' partial forces and torques.
