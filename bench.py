@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 METRIC = "MLUPS and % of HBM roofline; mixed-precision vs FP32 at stated error"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_piston_duct_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1703_05158_amd", "csrc", "lbm_step.hip")
+REFERENCE = os.path.join(ROOT, "tests", "golden", "duct_reference.npz")
 
 
 def kernel_sha():
@@ -71,6 +72,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--static", action="store_true", help="bodies fixed (no per-step re-rasterisation)")
+    ap.add_argument("--no-mixed", dest="mixed", action="store_false",
+                    help="skip the FP16/BF16 runs and their error against the stored FP64 run")
     ap.add_argument("--cpu-steps", type=int, default=15, help="oracle sample steps (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("OMP_NUM_THREADS", "16")))
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -95,13 +98,53 @@ def main():
     import torch
 
     import lbm_workloads as W
-    from paper_1703_05158_amd import Lattice
 
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
     case = W.case_c1(drift=not args.static)
     K, Wm = args.steps, args.warmup
-    lat = Lattice.from_case(case, storage=args.storage, stream=stream.cuda_stream)
+    main_run = timed_run(case, args.storage, K, Wm)
+    N = case.n_nodes
+    out = {
+        "metric": METRIC, "value": main_run["value"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": K, "warmup": Wm, "ms_per_step": main_run["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": "piston_duct_128x128x512_4000spheres" + ("_static" if args.static else "_drift"),
+                   "nodes": N, "fluid_nodes": main_run["fluid_nodes"], "spheres": case.n_bodies,
+                   "walls": case.n_walls, "tau0": case.tau0, "smag_c": case.smag_c, "storage": args.storage,
+                   "per_step": "set_bodies_device + step + get_forces_device" if case.drift
+                   else "step + get_forces_device"},
+        "mflups": main_run["mflups"],
+        "roofline": main_run["roofline"],
+    }
+    if args.mixed and args.storage == "f32" and not args.static:
+        # the same workload with 16-bit deviation storage: throughput, speedup
+        # over the FP32 step, and the error against the stored FP64 run
+        mixed = {}
+        for st in ("f16", "bf16"):
+            r = timed_run(case, st, K, Wm)
+            mixed[st] = {"value": r["value"], "unit": "MLUPS", "ms_per_step": r["ms_per_step"],
+                         "speedup_vs_f32": round(r["value"] / main_run["value"], 3),
+                         "kernel_ms": r["roofline"]["kernel_ms"], "roofline_frac": r["roofline"]["frac"]}
+        errs = precision_errors(case)
+        if errs:
+            for st, e in errs.items():
+                mixed.setdefault(st, {})["error_vs_fp64"] = e
+        out["mixed_precision"] = mixed
+    if args.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps, args.cpu_threads)
+    print(json.dumps(out), flush=True)
+
+
+def timed_run(case, storage, K, Wm):
+    """Warm up, then time K steps of the case (per step: the bodies' table of
+    that step handed over on the device, the step, the forces copied into a
+    device history); the step kernel is timed with HIP events on its stream."""
+    import numpy as np
+    import torch
+    from paper_1703_05158_amd import Lattice
+
+    stream = torch.cuda.current_stream()
+    lat = Lattice.from_case(case, storage=storage, stream=stream.cuda_stream)
     nb = case.n_bodies
     nbt = nb + case.n_walls
     # per-step kinematics, resident in HBM before timing (the DEM's output)
@@ -138,34 +181,64 @@ def main():
     lat.close()
 
     N = case.n_nodes
-    sbytes = 4 if args.storage == "f32" else 2
+    sbytes = 4 if storage == "f32" else 2
     nf = 0.5 * (n_fluid + n_fluid_end)
     # algorithmic bytes of one step-kernel launch: every fluid node reads and
     # writes 19 populations; every node's owner code (2 B) is read once
     alg_bytes = 2 * 19 * sbytes * nf + 2 * N
     k_avg_s = kms / launches * 1e-3
     achieved = alg_bytes / k_avg_s / 1e9
-    traffic = measured_traffic(args.storage)
+    traffic = measured_traffic(storage)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
-            "kernel": f"k_step<{args.storage}>", "kernel_ms": round(k_avg_s * 1e3, 4),
+            "kernel": f"k_step<{storage}>", "kernel_ms": round(k_avg_s * 1e3, 4),
             "alg_bytes_per_launch": int(alg_bytes)}
-    out = {
-        "metric": METRIC, "value": round(N * K / dt / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
-        "steps": K, "warmup": Wm, "ms_per_step": round(dt / K * 1e3, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
-        "config": {"workload": "piston_duct_128x128x512_4000spheres" + ("_static" if args.static else "_drift"),
-                   "nodes": N, "fluid_nodes": int(nf), "spheres": nb, "walls": case.n_walls,
-                   "tau0": case.tau0, "smag_c": case.smag_c, "storage": args.storage,
-                   "per_step": "set_bodies_device + step + get_forces_device" if case.drift
-                   else "step + get_forces_device"},
-        "mflups": round(nf * K / dt / 1e6, 1),
-        "roofline": roof,
-    }
-    if args.cpu_steps > 0:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps, args.cpu_threads)
-    print(json.dumps(out), flush=True)
+    return {"value": round(N * K / dt / 1e6, 1), "ms_per_step": round(dt / K * 1e3, 4),
+            "mflups": round(nf * K / dt / 1e6, 1), "fluid_nodes": int(nf), "roofline": roof}
+
+
+def precision_errors(case):
+    """Density, velocity and force error of each storage format against the
+    stored FP64 oracle run of the same drifting duct (tests/golden), at the
+    steps it holds."""
+    import numpy as np
+    import torch
+    from paper_1703_05158_amd import Lattice
+
+    if not os.path.exists(REFERENCE):
+        return None
+    ref = np.load(REFERENCE)
+    marks = [int(s) for s in ref["steps"]]
+    nb = case.n_bodies
+    tabs = torch.empty((marks[-1], nb, 10), dtype=torch.float64, device="cuda")
+    for n in range(1, marks[-1] + 1):
+        X, V, Om, R = case.bodies_at(n)
+        tabs[n - 1] = torch.from_numpy(np.concatenate([X, V, Om, R[:, None]], 1))
+    stream = torch.cuda.current_stream()
+    res = {}
+    for st in ("f32", "f16", "bf16"):
+        lat = Lattice.from_case(case, storage=st, stream=stream.cuda_stream)
+        e = {}
+        for n in range(1, marks[-1] + 1):
+            lat.set_bodies_device(nb, tabs[n - 1])
+            lat.step(1)
+            if n in marks:
+                idx = ref[f"idx_{n}"]
+                rho, u = lat.get_macro()
+                ur = ref[f"u_{n}"]
+                umax = float(np.max(np.linalg.norm(ur, axis=0)))
+                F, _ = lat.get_forces()
+                Fr = ref[f"F_{n}"]
+                e[f"step_{n}"] = {
+                    "rho_abs": float(np.max(np.abs(rho.ravel()[idx] - ref[f"rho_{n}"]))),
+                    "u_abs": float(np.max(np.linalg.norm(u.reshape(3, -1)[:, idx] - ur, axis=0))),
+                    "u_max": umax,
+                    "force_rel": float(np.max(np.linalg.norm(F - Fr, axis=1)) / np.max(np.linalg.norm(Fr, axis=1))),
+                    "sampled_nodes": int(len(idx))}
+        res[st] = e
+        lat.close()
+    return res
 
 
 if __name__ == "__main__":

@@ -18,3 +18,12 @@ def orc():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session")
+def torch_stream():
+    """torch's current stream on cuda:0, handed to the library."""
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return torch.cuda.current_stream().cuda_stream

@@ -29,14 +29,6 @@ def _case_c1():
     return _C1["c"]
 
 
-@pytest.fixture(scope="module")
-def torch_stream():
-    import torch
-    assert torch.cuda.is_available()
-    torch.cuda.set_device(0)
-    return torch.cuda.current_stream().cuda_stream
-
-
 def _check(o, lat, pop_tol=POP_TOL, force_tol=FORCE_TOL):
     pe = pop_rel_err(o, lat)
     fe, te = force_rel_err(o, lat)
