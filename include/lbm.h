@@ -153,10 +153,13 @@ lbm_status lbm_set_bodies_device(lbm_handle h, int32_t n, const double *d_table)
 lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *u);
 
 /* Advance nsteps steps, asynchronously on the handle's stream.  Each step:
- * re-rasterise the spheres if they were set since the previous step, then
- * one fused kernel does pull streaming, interpolated bounce-back with the
- * moving-boundary term, moments, Smagorinsky tau*, BGK + Guo collision and
- * the per-body force/torque reduction.  Forces are those of the last step.
+ * re-rasterise the spheres if they were set since the previous step; the
+ * link pass closes every cut link with interpolated bounce-back and the
+ * moving-boundary term (Sec. 2.3), writing the value into the solid node's
+ * slot of the current state, and reduces the momentum exchange per body
+ * (force and torque); the step kernel then does pull streaming, moments,
+ * Smagorinsky tau*, BGK + Guo collision and the store (Sec. 2.2).  Forces
+ * are those of the last step.
  * With nan_guard_every = k the call synchronises every k steps and returns
  * LBM_ERR_UNSTABLE if a fluid node had a non-finite or non-positive density
  * or a non-finite velocity.  Errors: STATE (before lbm_init_fields), ARG
@@ -216,6 +219,52 @@ lbm_status lbm_count_fluid(lbm_handle h, int64_t *n_fluid);
  * milliseconds and the number of launches recorded.  Errors: ARG, HIP. */
 lbm_status lbm_profile(lbm_handle h, int32_t enable);
 lbm_status lbm_profile_read(lbm_handle h, double *ms_total, int64_t *launches);
+
+/* Tile shape of the step kernel, the nodes of one 256-thread workgroup:
+ * 0 = 64x2x2, 1 = 32x4x2, 2 = 32x2x4, 3 = 16x8x2 (x, y, z).  Results are the
+ * same bit for bit for every shape; only the speed differs.  lbm_create
+ * picks 64x2x2, or 32x4x2 when nx is a multiple of 32 but not of 64.
+ * Errors: ARG (shape out of range). */
+lbm_status lbm_set_tile(lbm_handle h, int32_t shape);
+lbm_status lbm_get_tile(lbm_handle h, int32_t *shape);
+
+/* Tile-shape autotuner.  Times trial_steps launches of the step kernel for
+ * every tile shape on the handle's current state (the launches write only
+ * the spare population buffer, so the state does not advance) and keeps the
+ * fastest.  cache_path (may be NULL) names a JSON object of integer shapes
+ * keyed "<gfx target>/<f32|f16|bf16>/<nx>x<ny>x<nz>": a key that is present
+ * is used without timing; a new result is written back.  shape (may be
+ * NULL) receives the chosen shape; us (may be NULL, 4 doubles) the average
+ * kernel time per shape in microseconds, -1 where not timed.  Synchronises.
+ * Errors: STATE (before lbm_init_fields, or bodies set since the last step),
+ * ARG (trial_steps < 1, cache not writable), HIP. */
+lbm_status lbm_autotune_tile(lbm_handle h, int32_t trial_steps, const char *cache_path, int32_t *shape,
+                             double *us);
+
+/* Batched stepping of independent lattices (a parameter sweep of many
+ * boxes): every step of the batch is one replay of a captured hipGraph that
+ * runs the link pass of all members as one persistent launch over their
+ * spheres and wall-link chunks, the wall totals, the step kernel of all
+ * members as one persistent launch over their tiles (each member with its
+ * own parameters and tile shape), and a parity flip.  Each member's results
+ * are bit for bit those of lbm_step on that member.
+ *   members : n distinct handles, all past lbm_init_fields, same storage,
+ *             no bodies set since their last step.  The batch borrows them:
+ *             they must outlive it, and their bodies and walls must not
+ *             change while it is used (build a new batch after a change).
+ *   stream  : hipStream_t for the batch's work, or NULL for a stream of its
+ *             own (default priority).
+ * lbm_batch_step waits for the members' queued work, replays the graph
+ * nsteps times, synchronises, and advances every member's state and step
+ * counter; forces of the last step are then read per member as usual.  The
+ * NaN guard does not run in batched steps.  Errors: ARG, STATE (a member not
+ * initialised, or with bodies pending), HIP, OOM (text in
+ * lbm_batch_last_error, or on the offending member's handle at creation). */
+typedef struct lbm_batch_ctx *lbm_batch;
+lbm_status lbm_batch_create(const lbm_handle *members, int32_t n, void *stream, lbm_batch *out);
+lbm_status lbm_batch_step(lbm_batch b, int32_t nsteps);
+const char *lbm_batch_last_error(lbm_batch b);
+void lbm_batch_destroy(lbm_batch b);
 
 #ifdef __cplusplus
 }

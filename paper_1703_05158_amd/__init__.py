@@ -18,7 +18,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "LBMError", "LBMConfig", "LBMInfo", "config", "Lattice",
+    "LBMError", "LBMConfig", "LBMInfo", "config", "Lattice", "Batch", "TILE_SHAPES",
     "lbm_version", "lbm_create", "lbm_destroy", "lbm_last_error", "lbm_set_stream",
     "lbm_set_walls", "lbm_set_bodies", "lbm_set_bodies_device", "lbm_init_fields",
     "lbm_step", "lbm_get_forces", "lbm_get_forces_device", "lbm_get_populations",
@@ -85,6 +85,13 @@ _sig = {
     "lbm_count_fluid": (ct.c_int, [_H, ct.POINTER(ct.c_int64)]),
     "lbm_profile": (ct.c_int, [_H, ct.c_int32]),
     "lbm_profile_read": (ct.c_int, [_H, _dp, ct.POINTER(ct.c_int64)]),
+    "lbm_set_tile": (ct.c_int, [_H, ct.c_int32]),
+    "lbm_get_tile": (ct.c_int, [_H, ct.POINTER(ct.c_int32)]),
+    "lbm_autotune_tile": (ct.c_int, [_H, ct.c_int32, ct.c_char_p, ct.POINTER(ct.c_int32), _dp]),
+    "lbm_batch_create": (ct.c_int, [ct.POINTER(_H), ct.c_int32, ct.c_void_p, ct.POINTER(_H)]),
+    "lbm_batch_step": (ct.c_int, [_H, ct.c_int32]),
+    "lbm_batch_last_error": (ct.c_char_p, [_H]),
+    "lbm_batch_destroy": (None, [_H]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_L, _name)
@@ -271,6 +278,52 @@ def lbm_profile_read(h):
     return ms.value, n.value
 
 
+TILE_SHAPES = ("64x2x2", "32x4x2", "32x2x4", "16x8x2")
+
+
+def lbm_set_tile(h, shape) -> None:
+    _check(h, _L.lbm_set_tile(h, TILE_SHAPES.index(shape) if isinstance(shape, str) else int(shape)))
+
+
+def lbm_get_tile(h) -> int:
+    s = ct.c_int32(0)
+    _check(h, _L.lbm_get_tile(h, ct.byref(s)))
+    return s.value
+
+
+def lbm_autotune_tile(h, trial_steps=10, cache_path=None):
+    """(chosen shape, per-shape kernel microseconds, -1 where not timed)."""
+    s = ct.c_int32(0)
+    us = (ct.c_double * len(TILE_SHAPES))()
+    path = None if cache_path is None else str(cache_path).encode()
+    _check(h, _L.lbm_autotune_tile(h, int(trial_steps), path, ct.byref(s), us))
+    return s.value, list(us)
+
+
+def _bcheck(b, st):
+    if st != 0:
+        msg = _L.lbm_batch_last_error(b)
+        raise LBMError(st, msg.decode() if msg else "")
+
+
+def lbm_batch_create(handles, stream=None):
+    arr = (_H * len(handles))(*handles)
+    out = _H()
+    st = _L.lbm_batch_create(arr, len(handles), _stream_ptr(stream), ct.byref(out))
+    if st != 0:
+        msgs = [(_L.lbm_last_error(h) or b"").decode() for h in handles]
+        raise LBMError(st, "; ".join(m for m in msgs if m))
+    return out
+
+
+def lbm_batch_step(b, nsteps=1) -> None:
+    _bcheck(b, _L.lbm_batch_step(b, int(nsteps)))
+
+
+def lbm_batch_destroy(b) -> None:
+    _L.lbm_batch_destroy(b)
+
+
 # ---- convenience object over one handle -----------------------------------------
 
 class Lattice:
@@ -366,3 +419,35 @@ class Lattice:
 
     def profile_read(self):
         return lbm_profile_read(self.h)
+
+    def set_tile(self, shape):
+        lbm_set_tile(self.h, shape)
+
+    @property
+    def tile(self):
+        return lbm_get_tile(self.h)
+
+    def autotune(self, trial_steps=10, cache_path=None):
+        return lbm_autotune_tile(self.h, trial_steps, cache_path)
+
+
+class Batch:
+    """Independent lattices stepped together (one graph replay per step)."""
+
+    def __init__(self, lattices, stream=None):
+        self.members = list(lattices)
+        self.b = lbm_batch_create([m.h for m in self.members], stream)
+
+    def step(self, nsteps=1):
+        lbm_batch_step(self.b, nsteps)
+
+    def close(self):
+        if self.b:
+            lbm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

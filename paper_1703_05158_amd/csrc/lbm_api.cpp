@@ -11,8 +11,12 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
+#include <sstream>
 #include <string>
 #include <utility>
 #include <vector>
@@ -113,6 +117,69 @@ GeomArgs geom(const lbm_ctx *h)
     return g;
 }
 
+void set_tile_shape(lbm_ctx *h, int shape)
+{
+    h->tile = shape;
+    h->ntx = (h->cfg.nx + kTileDims[shape][0] - 1) / kTileDims[shape][0];
+    h->nty = (h->cfg.ny + kTileDims[shape][1] - 1) / kTileDims[shape][1];
+    h->ntz = (h->cfg.nz + kTileDims[shape][2] - 1) / kTileDims[shape][2];
+    h->n_tiles = h->ntx * h->nty * h->ntz;
+}
+
+// Arguments of the step kernel (src/dst of the current state) and of the
+// link pass (pop of the current state, bodies of the current geometry).
+StepArgs step_args(const lbm_ctx *h)
+{
+    const lbm_config &c = h->cfg;
+    StepArgs a{};
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.nz = c.nz;
+    a.N = h->N;
+    a.Ns = h->Ns;
+    a.tile = h->tile;
+    a.ntx = h->ntx;
+    a.nty = h->nty;
+    a.ntz = h->ntz;
+    a.n_tiles = h->n_tiles;
+    a.tau0 = (float)c.tau0;
+    a.smag_k = (float)(18.0 * std::sqrt(2.0) * c.smag_c * c.smag_c);
+    a.rho0 = (float)c.rho0;
+    a.fx = (float)c.body_force[0];
+    a.fy = (float)c.body_force[1];
+    a.fz = (float)c.body_force[2];
+    a.own = h->own;
+    a.flag = c.nan_guard_every > 0 ? h->flag : nullptr;
+    a.src = h->pop[h->cur];
+    a.dst = h->pop[1 - h->cur];
+    return a;
+}
+
+LinkArgs link_args(const lbm_ctx *h)
+{
+    const lbm_config &c = h->cfg;
+    LinkArgs la{};
+    la.nx = c.nx;
+    la.ny = c.ny;
+    la.nz = c.nz;
+    la.Ns = h->Ns;
+    la.halfway = c.bb_mode == LBM_BB_HALFWAY;
+    la.rho0 = (float)c.rho0;
+    la.own = h->own;
+    la.walls = h->walls;
+    la.wl_node = h->wl_node;
+    la.wl_blk = h->wl_blk;
+    la.wl_wblk = h->wl_wblk;
+    la.wl_part = h->wl_part;
+    la.out = h->acc;
+    la.n_walls = h->n_walls;
+    la.n_wblk = h->n_walls > 0 ? h->n_wblk : 0;
+    la.nb = h->nb_state;
+    la.bodies = h->tab[h->ts];
+    la.pop = h->pop[h->cur];
+    return la;
+}
+
 // Rebuild the whole owner map: walls, then the spheres of tab[ts].
 lbm_status rasterize_full(lbm_ctx *h)
 {
@@ -167,6 +234,67 @@ lbm_status copy_sync(lbm_ctx *h, void *dst, const void *src, size_t bytes, hipMe
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
 }
+
+// gfx target of the current device ("gfx950"), the key prefix of the
+// tile-shape cache.
+std::string arch_name()
+{
+    int dev = 0;
+    hipDeviceProp_t p{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string s = p.gcnArchName;
+    const size_t c = s.find(':');
+    return c == std::string::npos ? s : s.substr(0, c);
+}
+
+// The tile-shape cache: a flat JSON object of string keys and integer values.
+std::map<std::string, int> read_cache(const char *path)
+{
+    std::map<std::string, int> m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    size_t i = 0;
+    while ((i = t.find('"', i)) != std::string::npos) {
+        const size_t j = t.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const size_t c = t.find(':', j);
+        if (c == std::string::npos) break;
+        char *e = nullptr;
+        const long v = std::strtol(t.c_str() + c + 1, &e, 10);
+        if (e == t.c_str() + c + 1) break;
+        m[t.substr(i + 1, j - i - 1)] = (int)v;
+        i = (size_t)(e - t.c_str());
+    }
+    return m;
+}
+
+bool write_cache(const char *path, const std::map<std::string, int> &m)
+{
+    std::ofstream f(path);
+    if (!f) return false;
+    f << "{\n";
+    size_t k = 0;
+    for (const auto &kv : m) f << "  \"" << kv.first << "\": " << kv.second << (++k < m.size() ? ",\n" : "\n");
+    f << "}\n";
+    return (bool)f;
+}
+
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t create()
+    {
+        hipError_t e = hipEventCreate(&e0);
+        return e == hipSuccess ? hipEventCreate(&e1) : e;
+    }
+    ~EventPair()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
 
 #define TRY(expr)                        \
     do {                                 \
@@ -281,12 +409,7 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
     const size_t popb = (size_t)kQ * h->Ns * h->sbytes;
     const int nbt = c.max_bodies + c.max_walls;
     // tile shape: 64 nodes along x unless x is a multiple of 32 but not of 64
-    h->tile = (c.nx % 64 != 0 && (c.nx % 32 == 0 || c.nx < 32)) ? kTile32x4x2 : kTile64x2x2;
-    const int TX = h->tile == kTile64x2x2 ? 64 : 32, TY = h->tile == kTile64x2x2 ? 2 : 4, TZ = 2;
-    h->ntx = (c.nx + TX - 1) / TX;
-    h->nty = (c.ny + TY - 1) / TY;
-    h->ntz = (c.nz + TZ - 1) / TZ;
-    h->n_tiles = h->ntx * h->nty * h->ntz;
+    set_tile_shape(h, (c.nx % 64 != 0 && (c.nx % 32 == 0 || c.nx < 32)) ? kTile32x4x2 : kTile64x2x2);
     if (dalloc(h, &h->pop[0], popb) != hipSuccess || dalloc(h, &h->pop[1], popb) != hipSuccess ||
         dalloc(h, &h->own, sizeof(uint16_t) * N + 4) != hipSuccess ||
         dalloc(h, &h->wall_map, (size_t)N) != hipSuccess ||
@@ -463,39 +586,8 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
     lbm_status st = check_ready(h);
     if (st != LBM_OK) return st;
     const lbm_config &c = h->cfg;
-    StepArgs a{};
-    a.nx = c.nx;
-    a.ny = c.ny;
-    a.nz = c.nz;
-    a.N = h->N;
-    a.Ns = h->Ns;
-    a.tile = h->tile;
-    a.ntx = h->ntx;
-    a.nty = h->nty;
-    a.ntz = h->ntz;
-    a.n_tiles = h->n_tiles;
-    a.tau0 = (float)c.tau0;
-    a.smag_k = (float)(18.0 * std::sqrt(2.0) * c.smag_c * c.smag_c);
-    a.rho0 = (float)c.rho0;
-    a.fx = (float)c.body_force[0];
-    a.fy = (float)c.body_force[1];
-    a.fz = (float)c.body_force[2];
-    a.own = h->own;
-    a.flag = c.nan_guard_every > 0 ? h->flag : nullptr;
-    LinkArgs la{};
-    la.nx = c.nx;
-    la.ny = c.ny;
-    la.nz = c.nz;
-    la.Ns = h->Ns;
-    la.halfway = c.bb_mode == LBM_BB_HALFWAY;
-    la.rho0 = (float)c.rho0;
-    la.own = h->own;
-    la.walls = h->walls;
-    la.wl_node = h->wl_node;
-    la.wl_blk = h->wl_blk;
-    la.wl_wblk = h->wl_wblk;
-    la.wl_part = h->wl_part;
-    la.out = h->acc;
+    StepArgs a = step_args(h);
+    LinkArgs la = link_args(h);
     for (int s = 0; s < nsteps; ++s) {
         if (h->dirty && (st = rasterize_update(h)) != LBM_OK) return st;
         la.n_walls = h->n_walls;
@@ -765,6 +857,259 @@ lbm_status lbm_profile_read(lbm_handle h, double *ms_total, int64_t *launches)
     }
     *ms_total = tot;
     *launches = (int64_t)h->prof_ev.size();
+    return LBM_OK;
+}
+
+
+lbm_status lbm_set_tile(lbm_handle h, int32_t shape)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (shape < 0 || shape >= kNumTileShapes)
+        return fail(h, LBM_ERR_ARG, "tile shape %d not in [0, %d)", shape, kNumTileShapes);
+    set_tile_shape(h, shape);
+    return LBM_OK;
+}
+
+lbm_status lbm_get_tile(lbm_handle h, int32_t *shape)
+{
+    if (!h || !shape) return h ? fail(h, LBM_ERR_ARG, "NULL output") : LBM_ERR_ARG;
+    *shape = h->tile;
+    return LBM_OK;
+}
+
+lbm_status lbm_autotune_tile(lbm_handle h, int32_t trial_steps, const char *cache_path, int32_t *shape_out,
+                             double *us)
+{
+    if (!h) return LBM_ERR_ARG;
+    TRY(check_ready(h));
+    if (trial_steps < 1) return fail(h, LBM_ERR_ARG, "trial_steps < 1");
+    if (h->dirty) return fail(h, LBM_ERR_STATE, "bodies were set since the last step; step before tuning");
+    if (us)
+        for (int k = 0; k < kNumTileShapes; ++k) us[k] = -1.0;
+    static const char *kStorage[] = {"f32", "f16", "bf16"};
+    const std::string key = arch_name() + "/" + kStorage[h->cfg.storage] + "/" + std::to_string(h->cfg.nx) + "x" +
+                            std::to_string(h->cfg.ny) + "x" + std::to_string(h->cfg.nz);
+    std::map<std::string, int> cache;
+    if (cache_path) {
+        cache = read_cache(cache_path);
+        auto it = cache.find(key);
+        if (it != cache.end() && it->second >= 0 && it->second < kNumTileShapes) {
+            set_tile_shape(h, it->second);
+            if (shape_out) *shape_out = it->second;
+            return LBM_OK;
+        }
+    }
+    // The step kernel reads the current state and writes only the spare
+    // buffer, so repeated launches leave the state as it is.
+    EventPair ev;
+    HIP_TRY(h, ev.create());
+    int best = h->tile;
+    double best_us = 1e300;
+    for (int k = 0; k < kNumTileShapes; ++k) {
+        set_tile_shape(h, k);
+        StepArgs a = step_args(h);
+        a.flag = nullptr;
+        HIP_TRY(h, launch_step(h->cfg.storage, a, h->stream));
+        HIP_TRY(h, hipEventRecord(ev.e0, h->stream));
+        for (int i = 0; i < trial_steps; ++i) HIP_TRY(h, launch_step(h->cfg.storage, a, h->stream));
+        HIP_TRY(h, hipEventRecord(ev.e1, h->stream));
+        HIP_TRY(h, hipEventSynchronize(ev.e1));
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, ev.e0, ev.e1));
+        const double t = 1e3 * ms / trial_steps;
+        if (us) us[k] = t;
+        if (t < best_us) {
+            best_us = t;
+            best = k;
+        }
+    }
+    set_tile_shape(h, best);
+    if (shape_out) *shape_out = best;
+    if (cache_path) {
+        cache[key] = best;
+        if (!write_cache(cache_path, cache)) return fail(h, LBM_ERR_ARG, "cannot write %s", cache_path);
+    }
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+struct lbm_batch_ctx {
+    std::vector<lbm_ctx *> m;
+    int storage = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    BatchMember *d_members = nullptr;
+    int *d_cur = nullptr;
+    int *h_cur = nullptr;          // pinned
+    BatchStepArgs bs{};
+    BatchLinkArgs bl{};
+    int grid_step = 0, grid_links = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string err;
+};
+
+namespace {
+
+lbm_status bfail(lbm_batch_ctx *b, lbm_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (b) b->err = buf;
+    return st;
+}
+
+#define BHIP_TRY(b, expr)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return bfail((b), e_ == hipErrorOutOfMemory ? LBM_ERR_OOM : LBM_ERR_HIP, "%s: %s", #expr, \
+                         hipGetErrorString(e_));                                                 \
+    } while (0)
+
+// Queue one batched step: link pass and wall totals of every member, the
+// persistent step kernel over every member's tiles, and the parity flip.
+lbm_status batch_enqueue(lbm_batch_ctx *b)
+{
+    BHIP_TRY(b, launch_batch_links(b->storage, b->bl, b->grid_links, b->stream));
+    BHIP_TRY(b, launch_batch_wall_forces(b->bl, b->stream));
+    BHIP_TRY(b, launch_batch_step(b->storage, b->bs, b->grid_step, b->stream));
+    BHIP_TRY(b, launch_batch_flip(b->d_cur, (int)b->m.size(), b->stream));
+    return LBM_OK;
+}
+
+lbm_status batch_build(lbm_batch_ctx *b)
+{
+    const int n = (int)b->m.size();
+    std::vector<BatchMember> hm((size_t)n);
+    int tiles = 0, items = 0, walls = 0;
+    for (int i = 0; i < n; ++i) {
+        lbm_ctx *h = b->m[(size_t)i];
+        BatchMember &bm = hm[(size_t)i];
+        bm.step = step_args(h);
+        bm.step.flag = nullptr;
+        bm.links = link_args(h);
+        bm.pop[0] = h->pop[0];
+        bm.pop[1] = h->pop[1];
+        bm.shape = h->tile;
+        bm.tile_begin = tiles;
+        bm.item_begin = items;
+        bm.wall_begin = walls;
+        tiles += h->n_tiles;
+        items += bm.links.nb + bm.links.n_wblk;
+        walls += h->n_walls;
+    }
+    BHIP_TRY(b, hipMalloc((void **)&b->d_members, sizeof(BatchMember) * (size_t)n));
+    BHIP_TRY(b, hipMalloc((void **)&b->d_cur, sizeof(int) * (size_t)n));
+    BHIP_TRY(b, hipHostMalloc((void **)&b->h_cur, sizeof(int) * (size_t)n));
+    BHIP_TRY(b, hipMemcpyAsync(b->d_members, hm.data(), sizeof(BatchMember) * (size_t)n, hipMemcpyHostToDevice,
+                               b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    b->bs = BatchStepArgs{b->d_members, b->d_cur, n, tiles};
+    b->bl = BatchLinkArgs{b->d_members, b->d_cur, n, items, walls};
+    int dev = 0, cus = 0;
+    BHIP_TRY(b, hipGetDevice(&dev));
+    BHIP_TRY(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    // persistent grids: a whole number of workgroups per XCD for the step
+    b->grid_step = std::max(8, std::min(cus * 8, (tiles + 7) / 8 * 8));
+    b->grid_links = std::max(1, std::min(cus * 4, items));
+    // capture one step in a graph, replayed once per step
+    BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    const lbm_status st = batch_enqueue(b);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->stream, &g);
+    if (st != LBM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    BHIP_TRY(b, ec);
+    b->graph = g;
+    BHIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbm_batch_destroy(lbm_batch b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_members) (void)hipFree(b->d_members);
+    if (b->d_cur) (void)hipFree(b->d_cur);
+    if (b->h_cur) (void)hipHostFree(b->h_cur);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+const char *lbm_batch_last_error(lbm_batch b) { return b ? b->err.c_str() : "null lbm_batch"; }
+
+lbm_status lbm_batch_create(const lbm_handle *members, int32_t n, void *stream, lbm_batch *out)
+{
+    if (!members || n < 1 || !out) return LBM_ERR_ARG;
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        lbm_ctx *h = members[i];
+        if (!h) return LBM_ERR_ARG;
+        if (!h->initialized) return fail(h, LBM_ERR_STATE, "batch member %d: lbm_init_fields has not been called", i);
+        if (h->dirty) return fail(h, LBM_ERR_STATE, "batch member %d: bodies set since the last step", i);
+        if (h->cfg.storage != members[0]->cfg.storage)
+            return fail(h, LBM_ERR_ARG, "batch member %d: storage differs from member 0", i);
+        for (int j = 0; j < i; ++j)
+            if (members[j] == h) return fail(h, LBM_ERR_ARG, "batch member %d repeats member %d", i, j);
+    }
+    lbm_batch_ctx *b = new (std::nothrow) lbm_batch_ctx();
+    if (!b) return LBM_ERR_OOM;
+    b->m.assign(members, members + n);
+    b->storage = members[0]->cfg.storage;
+    if (stream) {
+        b->stream = (hipStream_t)stream;
+    } else if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess) {
+        b->own_stream = true;
+    } else {
+        delete b;
+        return LBM_ERR_HIP;
+    }
+    for (lbm_ctx *h : b->m)
+        if (hipStreamSynchronize(h->stream) != hipSuccess) {
+            lbm_batch_destroy(b);
+            return LBM_ERR_HIP;
+        }
+    const lbm_status st = batch_build(b);
+    if (st != LBM_OK) {
+        for (lbm_ctx *h : b->m) h->err = "lbm_batch_create: " + b->err;
+        lbm_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch b, int32_t nsteps)
+{
+    if (!b) return LBM_ERR_ARG;
+    if (nsteps < 0) return bfail(b, LBM_ERR_ARG, "nsteps < 0");
+    const int n = (int)b->m.size();
+    for (int i = 0; i < n; ++i) {
+        lbm_ctx *h = b->m[(size_t)i];
+        if (h->dirty) return bfail(b, LBM_ERR_STATE, "member %d: bodies set since the batch was built", i);
+        BHIP_TRY(b, hipStreamSynchronize(h->stream));
+        b->h_cur[i] = h->cur;
+    }
+    BHIP_TRY(b, hipMemcpyAsync(b->d_cur, b->h_cur, sizeof(int) * (size_t)n, hipMemcpyHostToDevice, b->stream));
+    for (int s = 0; s < nsteps; ++s) BHIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    for (lbm_ctx *h : b->m) {
+        h->cur ^= nsteps & 1;
+        h->steps_done += nsteps;
+    }
     return LBM_OK;
 }
 

@@ -24,8 +24,9 @@ constexpr int kMaxWalls = 16;
 constexpr int kBlock = 256;       // threads of a workgroup
 constexpr int kWallChunk = 1024;  // wall links per workgroup of the link pass
 
-// Tile shapes of the step kernel (x extent; y and z fill 256 threads).
-enum TileShape { kTile64x2x2 = 0, kTile32x4x2 = 1 };
+// Tile shapes of the step kernel (256 nodes, one per thread).
+enum TileShape { kTile64x2x2 = 0, kTile32x4x2 = 1, kTile32x2x4 = 2, kTile16x8x2 = 3, kNumTileShapes = 4 };
+constexpr int kTileDims[kNumTileShapes][3] = {{64, 2, 2}, {32, 4, 2}, {32, 2, 4}, {16, 8, 2}};
 
 // Pull-collide step over the fluid nodes.  The populations pulled across a
 // cut link come from the solid node's slot, where the link pass has put the
@@ -63,6 +64,34 @@ struct LinkArgs {
     double *out;                  // [nb + n_walls][6]: F, T
 };
 
+// One lattice of a batch: its step arguments (src/dst filled in per step
+// from pop[cur]), its link-pass arguments (pop filled in likewise), its
+// tile shape and the first global tile and link-pass item it owns.
+struct BatchMember {
+    StepArgs step;
+    LinkArgs links;
+    void *pop[2];
+    int shape;
+    int tile_begin;               // global tile index of the member's tile 0
+    int item_begin;               // global link-pass item of the member's item 0 (spheres, then wall chunks)
+    int wall_begin;               // global wall index of the member's wall 0
+};
+
+struct BatchStepArgs {
+    const BatchMember *members;
+    const int *cur;               // [n]: member m's state is in pop[cur[m]]
+    int n;
+    int total_tiles;
+};
+
+struct BatchLinkArgs {
+    const BatchMember *members;
+    const int *cur;
+    int n;
+    int total_items;
+    int total_walls;
+};
+
 struct GeomArgs {
     int nx, ny, nz;
     int N;
@@ -81,6 +110,10 @@ struct GeomArgs {
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t s);
 hipError_t launch_links(int storage, const LinkArgs &a, hipStream_t s);
 hipError_t launch_wall_forces(const LinkArgs &a, hipStream_t s);
+hipError_t launch_batch_step(int storage, const BatchStepArgs &b, int grid, hipStream_t s);
+hipError_t launch_batch_links(int storage, const BatchLinkArgs &b, int grid, hipStream_t s);
+hipError_t launch_batch_wall_forces(const BatchLinkArgs &b, hipStream_t s);
+hipError_t launch_batch_flip(int *cur, int n, hipStream_t s);
 
 hipError_t launch_walls_init(const uint8_t *wall, uint16_t *own, int N, hipStream_t s);
 hipError_t launch_vacate(const GeomArgs &g, hipStream_t s);

@@ -415,7 +415,90 @@ __global__ __launch_bounds__(64) void k_wall_forces(LinkArgs a)
     if (lane < 6) a.out[6 * (a.nb + w) + lane] = v[lane];
 }
 
+// Largest m with key(m) <= g over the members of a batch.
+template <typename F>
+__device__ __forceinline__ int find_member(int n, int g, F key)
+{
+    int m = 0, top = n;
+    while (top - m > 1) {
+        const int mid = (m + top) >> 1;
+        if (key(mid) <= g) m = mid;
+        else top = mid;
+    }
+    return m;
+}
+
+// Persistent link pass over many lattices: item j of member m is sphere j
+// (j < nb) or wall chunk j - nb.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_batch_links(BatchLinkArgs b)
+{
+    __shared__ SphereLds L;
+    __shared__ double s_red[kWaves][6];
+    for (int g = blockIdx.x; g < b.total_items; g += gridDim.x) {
+        const int m = find_member(b.n, g, [&](int i) { return b.members[i].item_begin; });
+        const BatchMember &bm = b.members[m];
+        LinkArgs a = bm.links;
+        a.pop = bm.pop[b.cur[m]];
+        const int j = g - bm.item_begin;
+        if (j < a.nb)
+            sphere_block<S>(a, j, L, s_red);
+        else
+            wall_block<S>(a, j - a.nb, s_red);
+        __syncthreads();  // LDS is reused by the next item
+    }
+}
+
+// Wall totals of every member: one 64-thread workgroup per wall.
+__global__ __launch_bounds__(64) void k_batch_wall_forces(BatchLinkArgs b)
+{
+    const int g = blockIdx.x, lane = threadIdx.x;
+    const int m = find_member(b.n, g, [&](int i) { return b.members[i].wall_begin; });
+    const LinkArgs &a = b.members[m].links;
+    const int w = g - b.members[m].wall_begin;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int j = a.wl_wblk[w] + lane; j < a.wl_wblk[w + 1]; j += 64)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] += a.wl_part[6 * (size_t)j + c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] += __shfl_xor(v[c], off);
+    if (lane < 6) a.out[6 * (a.nb + w) + lane] = v[lane];
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_flip(int *cur, int n)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) cur[i] ^= 1;
+}
+
 }  // namespace
+
+hipError_t launch_batch_links(int storage, const BatchLinkArgs &b, int grid, hipStream_t s)
+{
+    if (b.total_items <= 0) return hipSuccess;
+    switch (storage) {
+    case 0: hipLaunchKernelGGL(k_batch_links<0>, dim3(grid), dim3(kBlock), 0, s, b); break;
+    case 1: hipLaunchKernelGGL(k_batch_links<1>, dim3(grid), dim3(kBlock), 0, s, b); break;
+    case 2: hipLaunchKernelGGL(k_batch_links<2>, dim3(grid), dim3(kBlock), 0, s, b); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_wall_forces(const BatchLinkArgs &b, hipStream_t s)
+{
+    if (b.total_walls <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_wall_forces, dim3(b.total_walls), dim3(64), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_flip(int *cur, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_flip, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, cur, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_links(int storage, const LinkArgs &a, hipStream_t s)
 {

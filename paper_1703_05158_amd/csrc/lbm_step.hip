@@ -35,8 +35,9 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks)
     return (b & 7) * per + (b >> 3);
 }
 
+// Tile t (TX x TY x TZ nodes, one per thread) of the lattice described by a.
 template <int S, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
+__device__ __forceinline__ void tile_step(const StepArgs &a, int t)
 {
     static_assert(TX * TY * TZ == kBlock, "tile must hold one workgroup");
     using St = Store<S>;
@@ -47,7 +48,6 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
     const int nx = a.nx, ny = a.ny, nz = a.nz;
 
     const int tid = threadIdx.x;
-    const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int r = t / a.ntx;
     const int x = (t - r * a.ntx) * TX + tid % TX;
     const int y = (r % a.nty) * TY + (tid / TX) % TY;
@@ -110,8 +110,17 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
         const float pxy = sxy - rho * ux * uy;
         const float pxz = sxz - rho * ux * uz;
         const float pyz = syz - rho * uy * uz;
-        const float Qn = pxx * pxx + pyy * pyy + pzz * pzz + 2.0f * (pxy * pxy + pxz * pxz + pyz * pyz);
-        const float tau = 0.5f * (a.tau0 + __builtin_sqrtf(a.tau0 * a.tau0 + a.smag_k * __builtin_sqrtf(Qn) * ir));
+        float tau;
+        if (S == 0) {
+            const float Qn = pxx * pxx + pyy * pyy + pzz * pzz + 2.0f * (pxy * pxy + pxz * pxz + pyz * pyz);
+            tau = 0.5f * (a.tau0 + __builtin_sqrtf(a.tau0 * a.tau0 + a.smag_k * __builtin_sqrtf(Qn) * ir));
+        } else {
+            // 16-bit storage: the strain-rate norm and tau* in FP64
+            const double Qn = (double)pxx * pxx + (double)pyy * pyy + (double)pzz * pzz +
+                              2.0 * ((double)pxy * pxy + (double)pxz * pxz + (double)pyz * pyz);
+            const double t0 = (double)a.tau0;
+            tau = (float)(0.5 * (t0 + sqrt(t0 * t0 + (double)a.smag_k * sqrt(Qn) / (double)rho)));
+        }
         const float om = __builtin_amdgcn_rcpf(tau);
         const float om1 = 1.0f - om;
         const float cf = 1.0f - 0.5f * om;
@@ -139,17 +148,74 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
     }
 }
 
+template <int S, int TX, int TY, int TZ>
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
+{
+    tile_step<S, TX, TY, TZ>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <int S>
+__device__ __forceinline__ void tile_step_shape(const StepArgs &a, int shape, int t)
+{
+    switch (shape) {
+    case kTile64x2x2: tile_step<S, 64, 2, 2>(a, t); break;
+    case kTile32x4x2: tile_step<S, 32, 4, 2>(a, t); break;
+    case kTile32x2x4: tile_step<S, 32, 2, 4>(a, t); break;
+    default: tile_step<S, 16, 8, 2>(a, t); break;
+    }
+}
+
+// Persistent step over the tiles of many lattices.  Member m owns the global
+// tiles [tile_begin[m], tile_begin[m + 1]); XCD k (workgroups k, k + 8, ...)
+// walks the k-th eighth of the global tile range, so that each XCD works on
+// neighbouring tiles of the same members.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_batch_step(BatchStepArgs b)
+{
+    const int xcd = blockIdx.x & 7, stride = gridDim.x >> 3;
+    const int lo = (int)((long long)b.total_tiles * xcd / 8), hi = (int)((long long)b.total_tiles * (xcd + 1) / 8);
+    for (int g = lo + (int)(blockIdx.x >> 3); g < hi; g += stride) {
+        int m = 0, top = b.n;  // largest m with tile_begin[m] <= g
+        while (top - m > 1) {
+            const int mid = (m + top) >> 1;
+            if (b.members[mid].tile_begin <= g) m = mid;
+            else top = mid;
+        }
+        const BatchMember &bm = b.members[m];
+        StepArgs a = bm.step;
+        const int c = b.cur[m];
+        a.src = bm.pop[c];
+        a.dst = bm.pop[c ^ 1];
+        tile_step_shape<S>(a, bm.shape, g - bm.tile_begin);
+    }
+}
+
 template <int S>
 hipError_t launch_step_s(const StepArgs &a, hipStream_t s)
 {
-    if (a.tile == kTile64x2x2)
-        hipLaunchKernelGGL((k_step<S, 64, 2, 2>), dim3(a.n_tiles), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_step<S, 32, 4, 2>), dim3(a.n_tiles), dim3(kBlock), 0, s, a);
+    switch (a.tile) {
+    case kTile64x2x2: hipLaunchKernelGGL((k_step<S, 64, 2, 2>), dim3(a.n_tiles), dim3(kBlock), 0, s, a); break;
+    case kTile32x4x2: hipLaunchKernelGGL((k_step<S, 32, 4, 2>), dim3(a.n_tiles), dim3(kBlock), 0, s, a); break;
+    case kTile32x2x4: hipLaunchKernelGGL((k_step<S, 32, 2, 4>), dim3(a.n_tiles), dim3(kBlock), 0, s, a); break;
+    case kTile16x8x2: hipLaunchKernelGGL((k_step<S, 16, 8, 2>), dim3(a.n_tiles), dim3(kBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t launch_batch_step(int storage, const BatchStepArgs &b, int grid, hipStream_t s)
+{
+    if (b.total_tiles <= 0) return hipSuccess;
+    switch (storage) {
+    case 0: hipLaunchKernelGGL(k_batch_step<0>, dim3(grid), dim3(kBlock), 0, s, b); break;
+    case 1: hipLaunchKernelGGL(k_batch_step<1>, dim3(grid), dim3(kBlock), 0, s, b); break;
+    case 2: hipLaunchKernelGGL(k_batch_step<2>, dim3(grid), dim3(kBlock), 0, s, b); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t s)
 {

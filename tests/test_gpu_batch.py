@@ -1,0 +1,125 @@
+"""Tile shapes, the tile-shape autotuner and batched stepping.
+
+Every tile shape runs the same per-node arithmetic, and the batched kernels
+run the per-tile and per-sphere device code of the single-lattice kernels,
+so results must agree bit for bit; the autotuner must leave the state as it
+found it.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import lbm_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _members():
+    """Small lattices of uneven size: spheres, walls, halfway links, forcing."""
+    return [
+        (W.case_box(n=(40, 36, 48), n_spheres=5, radius=(2.0, 4.0), tau0=0.62, smag_c=0.15,
+                    body_force=(3e-6, 0, 0), u_sigma=0.01, gap=1.5, seed=21), "bouzidi"),
+        (W.case_duct(nx=32, ny=32, nz=96, n_spheres=20, orifice_z=70, orifice_r_in=8, orifice_gap=3,
+                     pack_z=(6, 60), v_sigma=0.0, w_sigma=0.0, seed=22, drift=False), "bouzidi"),
+        (W.case_box(n=(24, 28, 20), n_spheres=2, radius=(3.0, 3.5), tau0=0.75, smag_c=0.1,
+                    body_force=(0, 1e-6, 0), u_sigma=0.02, seed=23), "halfway"),
+        (W.case_box(n=(64, 16, 16), n_spheres=0, tau0=0.55, smag_c=0.2, body_force=(1e-5, 0, 0),
+                    u_sigma=0.005, seed=24), "bouzidi"),
+    ]
+
+
+def _build(stream, storage="f32"):
+    from paper_1703_05158_amd import Lattice
+    return [Lattice.from_case(c, storage=storage, bb_mode=bb, stream=stream) for c, bb in _members()]
+
+
+def test_tile_shapes_bitwise(torch_stream):
+    from paper_1703_05158_amd import TILE_SHAPES, Lattice
+    case, _ = _members()[1]
+    ref = None
+    for shape in range(len(TILE_SHAPES)):
+        lat = Lattice.from_case(case, stream=torch_stream)
+        lat.set_tile(shape)
+        assert lat.tile == shape
+        lat.step(6)
+        P = lat.get_populations()
+        F, T = lat.get_forces()
+        if ref is None:
+            ref = (P, F, T)
+        else:
+            assert np.array_equal(P, ref[0]) and np.array_equal(F, ref[1]) and np.array_equal(T, ref[2])
+        lat.close()
+
+
+def test_autotune_leaves_state_and_uses_cache(torch_stream, tmp_path):
+    from paper_1703_05158_amd import TILE_SHAPES, Lattice
+    case, _ = _members()[0]
+    lat = Lattice.from_case(case, stream=torch_stream)
+    lat.step(2)
+    P0 = lat.get_populations()
+    F0, T0 = lat.get_forces()
+    cache = tmp_path / "tiles.json"
+    shape, us = lat.autotune(trial_steps=3, cache_path=cache)
+    assert 0 <= shape < len(TILE_SHAPES) and lat.tile == shape
+    assert all(t > 0 for t in us) and us[shape] == min(us)
+    assert np.array_equal(lat.get_populations(), P0)
+    F1, T1 = lat.get_forces()
+    assert np.array_equal(F1, F0) and np.array_equal(T1, T0)
+    d = json.loads(cache.read_text())
+    key = [k for k in d if k.endswith(f"/f32/{case.nx}x{case.ny}x{case.nz}")]
+    assert len(key) == 1 and d[key[0]] == shape
+    # a second lattice of the same size takes the cached shape without timing
+    lat2 = Lattice.from_case(case, stream=torch_stream)
+    lat2.set_tile((shape + 1) % len(TILE_SHAPES))
+    s2, us2 = lat2.autotune(trial_steps=3, cache_path=cache)
+    assert s2 == shape and lat2.tile == shape and all(t == -1 for t in us2)
+    lat.close()
+    lat2.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_batch_matches_single_lattices(torch_stream, storage):
+    from paper_1703_05158_amd import Batch
+    single = _build(torch_stream, storage)
+    batched = _build(torch_stream, storage)
+    batched[0].set_tile(1)
+    batched[3].set_tile(3)
+    b = Batch(batched, stream=torch_stream)
+    for k in (7, 4, 1):
+        for lat in single:
+            lat.step(k)
+        b.step(k)
+        for s, t in zip(single, batched):
+            assert np.array_equal(s.get_populations(), t.get_populations())
+            Fs, Ts = s.get_forces()
+            Ft, Tt = t.get_forces()
+            assert np.array_equal(Fs, Ft) and np.array_equal(Ts, Tt)
+            assert s.info()["steps_done"] == t.info()["steps_done"]
+    # members continue on their own after batched steps
+    for s, t in zip(single, batched):
+        s.step(3)
+        t.step(3)
+        assert np.array_equal(s.get_populations(), t.get_populations())
+    b.close()
+    for lat in single + batched:
+        lat.close()
+
+
+def test_batch_rejects_bad_members(torch_stream):
+    from paper_1703_05158_amd import Batch, LBMError, Lattice
+    (case, _), (case2, _) = _members()[0], _members()[2]
+    a = Lattice.from_case(case, stream=torch_stream)
+    b16 = Lattice.from_case(case2, storage="f16", stream=torch_stream)
+    with pytest.raises(LBMError):
+        Batch([a, b16])
+    with pytest.raises(LBMError):
+        Batch([a, a])
+    raw = Lattice.from_case(case2, stream=torch_stream, init=False)
+    with pytest.raises(LBMError):
+        Batch([a, raw])
+    a.set_bodies(*case.bodies_at(1))
+    with pytest.raises(LBMError):
+        Batch([a])
+    for lat in (a, b16, raw):
+        lat.close()
