@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--static", action="store_true", help="bodies fixed (no per-step re-rasterisation)")
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
                     help="skip the FP16/BF16 runs and their error against the stored FP64 run")
+    ap.add_argument("--no-sweep", dest="sweep", action="store_false",
+                    help="skip the batched 48-instance parameter sweep")
+    ap.add_argument("--sweep-steps", type=int, default=500)
     ap.add_argument("--cpu-steps", type=int, default=15, help="oracle sample steps (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("OMP_NUM_THREADS", "16")))
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -130,9 +133,59 @@ def main():
             for st, e in errs.items():
                 mixed.setdefault(st, {})["error_vs_fp64"] = e
         out["mixed_precision"] = mixed
+    if args.sweep and args.storage == "f32" and not args.static:
+        out["batched_sweep"] = sweep_run(args.sweep_steps)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps, args.cpu_threads)
     print(json.dumps(out), flush=True)
+
+
+def sweep_run(steps, warmup=20):
+    """The 48-instance parameter sweep (periodic boxes of five sizes, static
+    spheres, FP32): tile shapes autotuned per box size, then the instances
+    stepped one after another with plain launches, then the same instances
+    stepped as one batch (one graph replay per step)."""
+    import tempfile
+
+    import torch
+
+    import lbm_workloads as W
+    from paper_1703_05158_amd import TILE_SHAPES, Batch, Lattice
+
+    stream = torch.cuda.current_stream()
+    cases = W.case_sweep_instances()
+    lats = [Lattice.from_case(c, stream=stream.cuda_stream) for c in cases]
+    nodes = sum(c.n_nodes for c in cases)
+    tiles = {}
+    with tempfile.TemporaryDirectory() as d:
+        cache = os.path.join(d, "tiles.json")
+        for c, lat in zip(cases, lats):
+            shape, _ = lat.autotune(trial_steps=5, cache_path=cache)
+            tiles[f"{c.nx}x{c.ny}x{c.nz}"] = TILE_SHAPES[shape]
+    for lat in lats:
+        lat.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lat in lats:
+        lat.step(steps)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    batch = Batch(lats, stream=stream)
+    bshape, _ = batch.autotune(trial_steps=5)
+    tiles["batch"] = TILE_SHAPES[bshape]
+    batch.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    batch.close()
+    for lat in lats:
+        lat.close()
+    return {"instances": len(cases), "nodes": nodes, "steps": steps, "tiles": tiles,
+            "sequential_mlups": round(nodes * steps / t_seq / 1e6, 1),
+            "batched_mlups": round(nodes * steps / t_bat / 1e6, 1),
+            "speedup": round(t_seq / t_bat, 3)}
 
 
 def timed_run(case, storage, K, Wm):

@@ -246,10 +246,11 @@ lbm_status lbm_autotune_tile(lbm_handle h, int32_t trial_steps, const char *cach
  * runs the link pass of all members as one persistent launch over their
  * spheres and wall-link chunks, the wall totals, the step kernel of all
  * members as one persistent launch over their tiles (each member with its
- * own parameters and tile shape), and a parity flip.  Each member's results
+ * own parameters), and a parity flip.  Each member's results
  * are bit for bit those of lbm_step on that member.
  *   members : n distinct handles, all past lbm_init_fields, same storage,
- *             no bodies set since their last step.  The batch borrows them:
+ *             no bodies set since their last step (their own tile shapes
+ *             do not matter: the batch has one, see below).  The batch borrows them:
  *             they must outlive it, and their bodies and walls must not
  *             change while it is used (build a new batch after a change).
  *   stream  : hipStream_t for the batch's work, or NULL for a stream of its
@@ -265,6 +266,18 @@ lbm_status lbm_batch_create(const lbm_handle *members, int32_t n, void *stream, 
 lbm_status lbm_batch_step(lbm_batch b, int32_t nsteps);
 const char *lbm_batch_last_error(lbm_batch b);
 void lbm_batch_destroy(lbm_batch b);
+
+/* Tile shape of the batched step kernel (one shape for all members, same
+ * numbering as lbm_set_tile; 64x2x2 when every nx is a multiple of 64, else
+ * 32x4x2 at creation).  lbm_batch_autotune times trial_steps launches of the
+ * batched step kernel for every shape on the members' current states (the
+ * launches write only the spare buffers, so no state advances), keeps the
+ * fastest and returns it in shape (may be NULL), with the time per launch
+ * in microseconds for each shape in us (may be NULL, 4 doubles).  Both
+ * rebuild the captured graph.  Errors: ARG, STATE, HIP. */
+lbm_status lbm_batch_set_tile(lbm_batch b, int32_t shape);
+lbm_status lbm_batch_get_tile(lbm_batch b, int32_t *shape);
+lbm_status lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t *shape, double *us);
 
 #ifdef __cplusplus
 }

@@ -252,7 +252,10 @@ def case_sweep_instances(n_instances: int = 48, seed: int = 3, steps: int = 500)
     [0.52, 0.8], C in [0.1, 0.2], body force magnitude in [1e-7, 1e-5] along
     x, packing fraction in [0, 0.35] of spheres with radius uniform in
     [2, 5]; the sphere count is min(1500, round(phi * V / E[V_sphere])) with
-    E[V_sphere] = (4/3) pi E[R^3], E[R^3] = (5^4 - 2^4) / (4 * 3).
+    E[V_sphere] = (4/3) pi E[R^3], E[R^3] = (5^4 - 2^4) / (4 * 3).  Spheres
+    are placed by random sequential addition without a surface gap (they may
+    touch, never overlap): with a one-cell gap the densest instances (phi
+    near 0.35) cannot be packed that way.
     """
     out = []
     ev = 4.0 / 3.0 * np.pi * (5.0 ** 4 - 2.0 ** 4) / (4.0 * 3.0)
@@ -265,7 +268,8 @@ def case_sweep_instances(n_instances: int = 48, seed: int = 3, steps: int = 500)
         phi = float(rng.uniform(0.0, 0.35))
         nsph = int(min(1500, round(phi * nx * ny * nz / ev)))
         R = 2.0 + 3.0 * rng.random(nsph)
-        X = rsa_pack(rng, R, (0, 0, 0), (nx, ny, nz), gap=1.0, box=(nx, ny, nz)) if nsph else np.zeros((0, 3))
+        X = (rsa_pack(rng, R, (0, 0, 0), (nx, ny, nz), gap=0.0, box=(nx, ny, nz), max_tries=400000)
+             if nsph else np.zeros((0, 3)))
         out.append(Case(name=f"sweep{k}_{nx}x{ny}x{nz}_{nsph}spheres", nx=nx, ny=ny, nz=nz,
                         tau0=tau0, smag_c=cs, body_force=(fmag, 0.0, 0.0), X=X,
                         V=np.zeros((nsph, 3)), Omega=np.zeros((nsph, 3)), R=R, steps=steps))

@@ -92,6 +92,9 @@ _sig = {
     "lbm_batch_step": (ct.c_int, [_H, ct.c_int32]),
     "lbm_batch_last_error": (ct.c_char_p, [_H]),
     "lbm_batch_destroy": (None, [_H]),
+    "lbm_batch_set_tile": (ct.c_int, [_H, ct.c_int32]),
+    "lbm_batch_get_tile": (ct.c_int, [_H, ct.POINTER(ct.c_int32)]),
+    "lbm_batch_autotune": (ct.c_int, [_H, ct.c_int32, ct.POINTER(ct.c_int32), _dp]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_L, _name)
@@ -324,6 +327,24 @@ def lbm_batch_destroy(b) -> None:
     _L.lbm_batch_destroy(b)
 
 
+def lbm_batch_set_tile(b, shape) -> None:
+    _bcheck(b, _L.lbm_batch_set_tile(b, TILE_SHAPES.index(shape) if isinstance(shape, str) else int(shape)))
+
+
+def lbm_batch_get_tile(b) -> int:
+    s = ct.c_int32(0)
+    _bcheck(b, _L.lbm_batch_get_tile(b, ct.byref(s)))
+    return s.value
+
+
+def lbm_batch_autotune(b, trial_steps=5):
+    """(chosen shape, per-shape microseconds per batched step-kernel launch)."""
+    s = ct.c_int32(0)
+    us = (ct.c_double * len(TILE_SHAPES))()
+    _bcheck(b, _L.lbm_batch_autotune(b, int(trial_steps), ct.byref(s), us))
+    return s.value, list(us)
+
+
 # ---- convenience object over one handle -----------------------------------------
 
 class Lattice:
@@ -440,6 +461,16 @@ class Batch:
 
     def step(self, nsteps=1):
         lbm_batch_step(self.b, nsteps)
+
+    def set_tile(self, shape):
+        lbm_batch_set_tile(self.b, shape)
+
+    @property
+    def tile(self):
+        return lbm_batch_get_tile(self.b)
+
+    def autotune(self, trial_steps=5):
+        return lbm_batch_autotune(self.b, trial_steps)
 
     def close(self):
         if self.b:

@@ -944,6 +944,7 @@ struct lbm_batch_ctx {
     int *h_cur = nullptr;          // pinned
     BatchStepArgs bs{};
     BatchLinkArgs bl{};
+    int shape = kTile64x2x2;       // tile shape of the batched step kernel
     int grid_step = 0, grid_links = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -977,14 +978,29 @@ lbm_status batch_enqueue(lbm_batch_ctx *b)
 {
     BHIP_TRY(b, launch_batch_links(b->storage, b->bl, b->grid_links, b->stream));
     BHIP_TRY(b, launch_batch_wall_forces(b->bl, b->stream));
-    BHIP_TRY(b, launch_batch_step(b->storage, b->bs, b->grid_step, b->stream));
+    BHIP_TRY(b, launch_batch_step(b->storage, b->shape, b->bs, b->grid_step, b->stream));
     BHIP_TRY(b, launch_batch_flip(b->d_cur, (int)b->m.size(), b->stream));
     return LBM_OK;
 }
 
+void batch_release(lbm_batch_ctx *b)
+{
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_members) (void)hipFree(b->d_members);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->d_members = nullptr;
+}
+
+// Member tables for the batch's tile shape, persistent grid sizes, and the
+// captured graph of one step.
 lbm_status batch_build(lbm_batch_ctx *b)
 {
+    batch_release(b);
     const int n = (int)b->m.size();
+    const int TX = kTileDims[b->shape][0], TY = kTileDims[b->shape][1], TZ = kTileDims[b->shape][2];
     std::vector<BatchMember> hm((size_t)n);
     int tiles = 0, items = 0, walls = 0;
     for (int i = 0; i < n; ++i) {
@@ -992,20 +1008,24 @@ lbm_status batch_build(lbm_batch_ctx *b)
         BatchMember &bm = hm[(size_t)i];
         bm.step = step_args(h);
         bm.step.flag = nullptr;
+        bm.step.tile = b->shape;
+        bm.step.ntx = (h->cfg.nx + TX - 1) / TX;
+        bm.step.nty = (h->cfg.ny + TY - 1) / TY;
+        bm.step.ntz = (h->cfg.nz + TZ - 1) / TZ;
+        bm.step.n_tiles = bm.step.ntx * bm.step.nty * bm.step.ntz;
         bm.links = link_args(h);
         bm.pop[0] = h->pop[0];
         bm.pop[1] = h->pop[1];
-        bm.shape = h->tile;
         bm.tile_begin = tiles;
         bm.item_begin = items;
         bm.wall_begin = walls;
-        tiles += h->n_tiles;
+        tiles += bm.step.n_tiles;
         items += bm.links.nb + bm.links.n_wblk;
         walls += h->n_walls;
     }
     BHIP_TRY(b, hipMalloc((void **)&b->d_members, sizeof(BatchMember) * (size_t)n));
-    BHIP_TRY(b, hipMalloc((void **)&b->d_cur, sizeof(int) * (size_t)n));
-    BHIP_TRY(b, hipHostMalloc((void **)&b->h_cur, sizeof(int) * (size_t)n));
+    if (!b->d_cur) BHIP_TRY(b, hipMalloc((void **)&b->d_cur, sizeof(int) * (size_t)n));
+    if (!b->h_cur) BHIP_TRY(b, hipHostMalloc((void **)&b->h_cur, sizeof(int) * (size_t)n));
     BHIP_TRY(b, hipMemcpyAsync(b->d_members, hm.data(), sizeof(BatchMember) * (size_t)n, hipMemcpyHostToDevice,
                                b->stream));
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
@@ -1014,9 +1034,11 @@ lbm_status batch_build(lbm_batch_ctx *b)
     int dev = 0, cus = 0;
     BHIP_TRY(b, hipGetDevice(&dev));
     BHIP_TRY(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    // persistent grids: a whole number of workgroups per XCD for the step
-    b->grid_step = std::max(8, std::min(cus * 8, (tiles + 7) / 8 * 8));
-    b->grid_links = std::max(1, std::min(cus * 4, items));
+    // persistent grids: as many workgroups as are resident at once (a
+    // whole number per XCD for the step kernel)
+    const int rs = batch_step_blocks_per_cu(b->storage, b->shape), rl = batch_links_blocks_per_cu(b->storage);
+    b->grid_step = std::max(8, std::min(cus * rs / 8 * 8, (tiles + 7) / 8 * 8));
+    b->grid_links = std::max(1, std::min(cus * rl, items));
     // capture one step in a graph, replayed once per step
     BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     const lbm_status st = batch_enqueue(b);
@@ -1039,10 +1061,7 @@ extern "C" {
 void lbm_batch_destroy(lbm_batch b)
 {
     if (!b) return;
-    if (b->stream) (void)hipStreamSynchronize(b->stream);
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    if (b->d_members) (void)hipFree(b->d_members);
+    batch_release(b);
     if (b->d_cur) (void)hipFree(b->d_cur);
     if (b->h_cur) (void)hipHostFree(b->h_cur);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -1069,6 +1088,10 @@ lbm_status lbm_batch_create(const lbm_handle *members, int32_t n, void *stream, 
     if (!b) return LBM_ERR_OOM;
     b->m.assign(members, members + n);
     b->storage = members[0]->cfg.storage;
+    b->shape = kTile32x4x2;
+    bool all64 = true;
+    for (lbm_ctx *h : b->m) all64 = all64 && h->cfg.nx % 64 == 0;
+    if (all64) b->shape = kTile64x2x2;
     if (stream) {
         b->stream = (hipStream_t)stream;
     } else if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess) {
@@ -1092,10 +1115,13 @@ lbm_status lbm_batch_create(const lbm_handle *members, int32_t n, void *stream, 
     return LBM_OK;
 }
 
-lbm_status lbm_batch_step(lbm_batch b, int32_t nsteps)
+}  // extern "C"
+
+namespace {
+
+// Wait for the members' queued work and load their state parities.
+lbm_status batch_sync_members(lbm_batch_ctx *b)
 {
-    if (!b) return LBM_ERR_ARG;
-    if (nsteps < 0) return bfail(b, LBM_ERR_ARG, "nsteps < 0");
     const int n = (int)b->m.size();
     for (int i = 0; i < n; ++i) {
         lbm_ctx *h = b->m[(size_t)i];
@@ -1104,6 +1130,71 @@ lbm_status lbm_batch_step(lbm_batch b, int32_t nsteps)
         b->h_cur[i] = h->cur;
     }
     BHIP_TRY(b, hipMemcpyAsync(b->d_cur, b->h_cur, sizeof(int) * (size_t)n, hipMemcpyHostToDevice, b->stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_set_tile(lbm_batch b, int32_t shape)
+{
+    if (!b) return LBM_ERR_ARG;
+    if (shape < 0 || shape >= kNumTileShapes) return bfail(b, LBM_ERR_ARG, "tile shape %d out of range", shape);
+    b->shape = shape;
+    return batch_build(b);
+}
+
+lbm_status lbm_batch_get_tile(lbm_batch b, int32_t *shape)
+{
+    if (!b || !shape) return b ? bfail(b, LBM_ERR_ARG, "NULL output") : LBM_ERR_ARG;
+    *shape = b->shape;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t *shape_out, double *us)
+{
+    if (!b) return LBM_ERR_ARG;
+    if (trial_steps < 1) return bfail(b, LBM_ERR_ARG, "trial_steps < 1");
+    if (us)
+        for (int k = 0; k < kNumTileShapes; ++k) us[k] = -1.0;
+    lbm_status st = batch_sync_members(b);
+    if (st != LBM_OK) return st;
+    // the batched step kernel reads every member's current state and writes
+    // only the spare buffers: repeated launches leave the states as they are
+    EventPair ev;
+    BHIP_TRY(b, ev.create());
+    int best = b->shape;
+    double best_us = 1e300;
+    for (int k = 0; k < kNumTileShapes; ++k) {
+        b->shape = k;
+        if ((st = batch_build(b)) != LBM_OK) return st;
+        BHIP_TRY(b, launch_batch_step(b->storage, k, b->bs, b->grid_step, b->stream));
+        BHIP_TRY(b, hipEventRecord(ev.e0, b->stream));
+        for (int i = 0; i < trial_steps; ++i)
+            BHIP_TRY(b, launch_batch_step(b->storage, k, b->bs, b->grid_step, b->stream));
+        BHIP_TRY(b, hipEventRecord(ev.e1, b->stream));
+        BHIP_TRY(b, hipEventSynchronize(ev.e1));
+        float ms = 0.f;
+        BHIP_TRY(b, hipEventElapsedTime(&ms, ev.e0, ev.e1));
+        const double t = 1e3 * ms / trial_steps;
+        if (us) us[k] = t;
+        if (t < best_us) {
+            best_us = t;
+            best = k;
+        }
+    }
+    b->shape = best;
+    if (shape_out) *shape_out = best;
+    return batch_build(b);
+}
+
+lbm_status lbm_batch_step(lbm_batch b, int32_t nsteps)
+{
+    if (!b) return LBM_ERR_ARG;
+    if (nsteps < 0) return bfail(b, LBM_ERR_ARG, "nsteps < 0");
+    lbm_status st = batch_sync_members(b);
+    if (st != LBM_OK) return st;
     for (int s = 0; s < nsteps; ++s) BHIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     for (lbm_ctx *h : b->m) {

@@ -64,14 +64,13 @@ struct LinkArgs {
     double *out;                  // [nb + n_walls][6]: F, T
 };
 
-// One lattice of a batch: its step arguments (src/dst filled in per step
-// from pop[cur]), its link-pass arguments (pop filled in likewise), its
-// tile shape and the first global tile and link-pass item it owns.
+// One lattice of a batch: its step arguments for the batch's tile shape
+// (src/dst filled in per step from pop[cur]), its link-pass arguments (pop
+// filled in likewise) and the first global tile and link-pass item it owns.
 struct BatchMember {
     StepArgs step;
     LinkArgs links;
     void *pop[2];
-    int shape;
     int tile_begin;               // global tile index of the member's tile 0
     int item_begin;               // global link-pass item of the member's item 0 (spheres, then wall chunks)
     int wall_begin;               // global wall index of the member's wall 0
@@ -110,7 +109,9 @@ struct GeomArgs {
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t s);
 hipError_t launch_links(int storage, const LinkArgs &a, hipStream_t s);
 hipError_t launch_wall_forces(const LinkArgs &a, hipStream_t s);
-hipError_t launch_batch_step(int storage, const BatchStepArgs &b, int grid, hipStream_t s);
+hipError_t launch_batch_step(int storage, int shape, const BatchStepArgs &b, int grid, hipStream_t s);
+int batch_step_blocks_per_cu(int storage, int shape);   // resident workgroups per CU of the persistent kernels
+int batch_links_blocks_per_cu(int storage);
 hipError_t launch_batch_links(int storage, const BatchLinkArgs &b, int grid, hipStream_t s);
 hipError_t launch_batch_wall_forces(const BatchLinkArgs &b, hipStream_t s);
 hipError_t launch_batch_flip(int *cur, int n, hipStream_t s);

@@ -435,12 +435,18 @@ __global__ __launch_bounds__(kBlock) void k_batch_links(BatchLinkArgs b)
 {
     __shared__ SphereLds L;
     __shared__ double s_red[kWaves][6];
+    int mb = 0, me = 0;
+    LinkArgs a{};
     for (int g = blockIdx.x; g < b.total_items; g += gridDim.x) {
-        const int m = find_member(b.n, g, [&](int i) { return b.members[i].item_begin; });
-        const BatchMember &bm = b.members[m];
-        LinkArgs a = bm.links;
-        a.pop = bm.pop[b.cur[m]];
-        const int j = g - bm.item_begin;
+        if (g < mb || g >= me) {  // the member of the previous item is kept
+            const int m = find_member(b.n, g, [&](int i) { return b.members[i].item_begin; });
+            const BatchMember &bm = b.members[m];
+            mb = bm.item_begin;
+            me = m + 1 < b.n ? b.members[m + 1].item_begin : b.total_items;
+            a = bm.links;
+            a.pop = bm.pop[b.cur[m]];
+        }
+        const int j = g - mb;
         if (j < a.nb)
             sphere_block<S>(a, j, L, s_red);
         else
@@ -474,6 +480,18 @@ __global__ __launch_bounds__(kBlock) void k_batch_flip(int *cur, int n)
 }
 
 }  // namespace
+
+int batch_links_blocks_per_cu(int storage)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (storage) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_links<0>, kBlock, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_links<1>, kBlock, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_links<2>, kBlock, 0); break;
+    }
+    return e == hipSuccess && n > 0 ? n : 1;
+}
 
 hipError_t launch_batch_links(int storage, const BatchLinkArgs &b, int grid, hipStream_t s)
 {

@@ -154,39 +154,36 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
     tile_step<S, TX, TY, TZ>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-template <int S>
-__device__ __forceinline__ void tile_step_shape(const StepArgs &a, int shape, int t)
-{
-    switch (shape) {
-    case kTile64x2x2: tile_step<S, 64, 2, 2>(a, t); break;
-    case kTile32x4x2: tile_step<S, 32, 4, 2>(a, t); break;
-    case kTile32x2x4: tile_step<S, 32, 2, 4>(a, t); break;
-    default: tile_step<S, 16, 8, 2>(a, t); break;
-    }
-}
-
-// Persistent step over the tiles of many lattices.  Member m owns the global
-// tiles [tile_begin[m], tile_begin[m + 1]); XCD k (workgroups k, k + 8, ...)
-// walks the k-th eighth of the global tile range, so that each XCD works on
-// neighbouring tiles of the same members.
-template <int S>
+// Persistent step over the tiles of many lattices, all with the batch's tile
+// shape.  Member m owns the global tiles [tile_begin[m], tile_begin[m + 1]);
+// XCD k (workgroups k, k + 8, ...) walks the k-th eighth of the global tile
+// range, so that each XCD works on neighbouring tiles of the same members.
+template <int S, int TX, int TY, int TZ>
 __global__ __launch_bounds__(kBlock) void k_batch_step(BatchStepArgs b)
 {
     const int xcd = blockIdx.x & 7, stride = gridDim.x >> 3;
     const int lo = (int)((long long)b.total_tiles * xcd / 8), hi = (int)((long long)b.total_tiles * (xcd + 1) / 8);
+    // the member of the previous tile is kept: a workgroup's next tile is
+    // usually in the same member
+    int mb = 0, me = 0;
+    StepArgs a{};
     for (int g = lo + (int)(blockIdx.x >> 3); g < hi; g += stride) {
-        int m = 0, top = b.n;  // largest m with tile_begin[m] <= g
-        while (top - m > 1) {
-            const int mid = (m + top) >> 1;
-            if (b.members[mid].tile_begin <= g) m = mid;
-            else top = mid;
+        if (g < mb || g >= me) {
+            int m = 0, top = b.n;  // largest m with tile_begin[m] <= g
+            while (top - m > 1) {
+                const int mid = (m + top) >> 1;
+                if (b.members[mid].tile_begin <= g) m = mid;
+                else top = mid;
+            }
+            const BatchMember &bm = b.members[m];
+            mb = bm.tile_begin;
+            me = m + 1 < b.n ? b.members[m + 1].tile_begin : b.total_tiles;
+            a = bm.step;
+            const int c = b.cur[m];
+            a.src = bm.pop[c];
+            a.dst = bm.pop[c ^ 1];
         }
-        const BatchMember &bm = b.members[m];
-        StepArgs a = bm.step;
-        const int c = b.cur[m];
-        a.src = bm.pop[c];
-        a.dst = bm.pop[c ^ 1];
-        tile_step_shape<S>(a, bm.shape, g - bm.tile_begin);
+        tile_step<S, TX, TY, TZ>(a, g - mb);
     }
 }
 
@@ -203,18 +200,47 @@ hipError_t launch_step_s(const StepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// The batched step kernel for a storage type and tile shape.
+template <int S>
+const void *batch_step_kernel_s(int shape)
+{
+    switch (shape) {
+    case kTile64x2x2: return (const void *)k_batch_step<S, 64, 2, 2>;
+    case kTile32x4x2: return (const void *)k_batch_step<S, 32, 4, 2>;
+    case kTile32x2x4: return (const void *)k_batch_step<S, 32, 2, 4>;
+    case kTile16x8x2: return (const void *)k_batch_step<S, 16, 8, 2>;
+    default: return nullptr;
+    }
+}
+
+const void *batch_step_kernel(int storage, int shape)
+{
+    switch (storage) {
+    case 0: return batch_step_kernel_s<0>(shape);
+    case 1: return batch_step_kernel_s<1>(shape);
+    case 2: return batch_step_kernel_s<2>(shape);
+    default: return nullptr;
+    }
+}
+
 }  // namespace
 
-hipError_t launch_batch_step(int storage, const BatchStepArgs &b, int grid, hipStream_t s)
+int batch_step_blocks_per_cu(int storage, int shape)
+{
+    const void *k = batch_step_kernel(storage, shape);
+    int n = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kBlock, 0) != hipSuccess || n < 1) return 1;
+    return n;
+}
+
+hipError_t launch_batch_step(int storage, int shape, const BatchStepArgs &b, int grid, hipStream_t s)
 {
     if (b.total_tiles <= 0) return hipSuccess;
-    switch (storage) {
-    case 0: hipLaunchKernelGGL(k_batch_step<0>, dim3(grid), dim3(kBlock), 0, s, b); break;
-    case 1: hipLaunchKernelGGL(k_batch_step<1>, dim3(grid), dim3(kBlock), 0, s, b); break;
-    case 2: hipLaunchKernelGGL(k_batch_step<2>, dim3(grid), dim3(kBlock), 0, s, b); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    const void *k = batch_step_kernel(storage, shape);
+    if (!k) return hipErrorInvalidValue;
+    BatchStepArgs arg = b;
+    void *args[] = {&arg};
+    return hipLaunchKernel(k, dim3(grid), dim3(kBlock), args, 0, s);
 }
 
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t s)

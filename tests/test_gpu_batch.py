@@ -83,10 +83,12 @@ def test_batch_matches_single_lattices(torch_stream, storage):
     from paper_1703_05158_amd import Batch
     single = _build(torch_stream, storage)
     batched = _build(torch_stream, storage)
-    batched[0].set_tile(1)
-    batched[3].set_tile(3)
+    single[0].set_tile(1)
+    single[3].set_tile(3)
     b = Batch(batched, stream=torch_stream)
-    for k in (7, 4, 1):
+    for k, shape in ((7, 0), (4, 3), (1, 2), (2, 1)):
+        b.set_tile(shape)
+        assert b.tile == shape
         for lat in single:
             lat.step(k)
         b.step(k)
@@ -103,6 +105,24 @@ def test_batch_matches_single_lattices(torch_stream, storage):
         assert np.array_equal(s.get_populations(), t.get_populations())
     b.close()
     for lat in single + batched:
+        lat.close()
+
+
+def test_batch_autotune_leaves_states(torch_stream):
+    from paper_1703_05158_amd import TILE_SHAPES, Batch
+    lats = _build(torch_stream)
+    for lat in lats:
+        lat.step(2)
+    P0 = [lat.get_populations() for lat in lats]
+    b = Batch(lats, stream=torch_stream)
+    shape, us = b.autotune(trial_steps=3)
+    assert 0 <= shape < len(TILE_SHAPES) and b.tile == shape
+    assert all(t > 0 for t in us) and us[shape] == min(us)
+    for lat, P in zip(lats, P0):
+        assert np.array_equal(lat.get_populations(), P)
+    b.step(3)
+    b.close()
+    for lat in lats:
         lat.close()
 
 
