@@ -61,7 +61,11 @@ def lib():
         body4 = [_dp, _dp, _dp, _dp]
         walls = [ct.c_int, _dp, _dp]
         L.orc_stream.argtypes = ([_ip, _dp, ct.c_int, _dp, _ip, _ip, ct.c_int] + body4 +
-                                 [ct.c_int] + body4 + walls + [_dp, _dp, _dp])
+                                 [ct.c_int] + body4 + walls + [ct.c_int, _dp, _dp, _dp])
+        L.orc_zieb_inflow.argtypes = [_ip, _dp, _ip, _dp, ct.c_int, _dp]
+        L.orc_zieb_density.argtypes = [ct.c_double] * 6
+        L.orc_zieb_density.restype = ct.c_double
+        L.orc_zieb.argtypes = [_ip, ct.c_int, ct.c_double, _ip, _dp, _dp]
         L.orc_collide.argtypes = [_ip, _dp, _ip, ct.c_int] + body4 + walls + [_dp, _dp]
         L.orc_init.argtypes = ([_ip, ct.c_double, _ip, ct.c_int] + body4 + walls +
                                [ct.c_void_p, ct.c_void_p, _dp])
@@ -125,6 +129,7 @@ class Oracle:
         self.F = np.zeros((0, 3))
         self.T = np.zeros((0, 3))
         self.steps_done = 0
+        self.zieb = None
         self.own = self._owner(self._bodies)
 
     @classmethod
@@ -173,6 +178,19 @@ class Oracle:
     def _wargs(self):
         return [self.n_walls, self.Uw.reshape(-1), self.Ref.reshape(-1)]
 
+    def set_zieb(self, z_s, area, volume, v_piston):
+        """Virtual-cylinder inflow (Sec. 2.6) at the plane z = z_s; the layer
+        z_s - 1 stands for the removed domain.  The cylinder density starts
+        at the plane's mean density of the initial state."""
+        self.zieb = dict(z=int(z_s), area=float(area), volume=float(volume), vp=float(v_piston),
+                         rho=None, H=0.0)
+
+    def zieb_inflow(self):
+        """(v_f, mean density) of the current state at the ZIEB plane."""
+        out = np.zeros(2)
+        lib().orc_zieb_inflow(self.dims, self.prm, self._state_own(), self.P, self.zieb["z"], out)
+        return float(out[0]), float(out[1])
+
     def init_fields(self, rho=None, u=None):
         self.P = np.zeros(19 * self.N)
         r = _f64(rho).reshape(-1) if rho is not None else None
@@ -188,14 +206,26 @@ class Oracle:
 
     # -- stepping -------------------------------------------------------
     def stream(self):
-        """Streaming + boundary stage only: (f [19,N] at fluid nodes, F, T)."""
+        """Streaming + boundary stage only: (f [19,N] at fluid nodes, F, T).
+        With a ZIEB plane, its update of the cylinder density and of the
+        plane's populations is part of this stage."""
         nbt = self._bodies["n"] + self.n_walls
         f = np.full(19 * self.N, np.nan)
         F = np.zeros(max(nbt, 1) * 3)
         T = np.zeros(max(nbt, 1) * 3)
+        zz = self.zieb["z"] if self.zieb else -1
+        if self.zieb:
+            z = self.zieb
+            vf, rbar = self.zieb_inflow()
+            if z["rho"] is None:
+                z["rho"] = rbar
+            z["rho_next"] = lib().orc_zieb_density(z["rho"], z["vp"], vf, z["area"], z["volume"], z["H"])
+            z["vf"] = vf
         lib().orc_stream(self.dims, self.prm, self.halfway, self.P, self.own_prev, self.own,
                          *self._bargs(self._bodies_prev), *self._bargs(self._bodies),
-                         *self._wargs(), f, F, T)
+                         *self._wargs(), zz, f, F, T)
+        if self.zieb:
+            lib().orc_zieb(self.dims, zz, self.zieb["rho_next"], self.own, self.P, f)
         return f, F[:3 * nbt].reshape(nbt, 3), T[:3 * nbt].reshape(nbt, 3)
 
     def step(self, nsteps=1):
@@ -208,6 +238,9 @@ class Oracle:
                               *self._wargs(), f, Pn)
             self.P = Pn
             self.F, self.T = F, T
+            if self.zieb:
+                self.zieb["rho"] = self.zieb["rho_next"]
+                self.zieb["H"] += self.zieb["vp"]
             self.own_prev = self.own.copy()
             self._bodies_prev = self._bodies
             self.steps_done += 1

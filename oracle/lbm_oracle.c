@@ -197,7 +197,7 @@ int orc_stream(const int *dims, const double *prm, int halfway,
                const double *P, const int32_t *own_prev, const int32_t *own_cur,
                int nb_prev, const double *Xp, const double *Vp, const double *Wp, const double *Rp,
                int nb, const double *X, const double *V, const double *W, const double *R,
-               int n_walls, const double *Uw, const double *Ref,
+               int n_walls, const double *Uw, const double *Ref, int zieb_z,
                double *f, double *F, double *T)
 {
     const int nx = dims[0], ny = dims[1], nz = dims[2];
@@ -244,6 +244,9 @@ int orc_stream(const int *dims, const double *prm, int halfway,
                 f[n] = Ph[n];  /* rest population stays */
                 for (int k = 1; k < Q19; ++k) {
                     int i = opposite(k);  /* population that arrives from x + c_k */
+                    /* ZIEB plane (Sec. 2.6): nothing arrives from the virtual
+                     * domain below it; orc_zieb fills these directions */
+                    if (z == zieb_z && CZ[i] == 1) continue;
                     long ns = wrap(x + CX[k], nx) + (long)nx * (wrap(y + CY[k], ny) + (long)ny * wrap(z + CZ[k], nz));
                     int o = own_cur[ns];
                     if (o < 0) {  /* plain streaming: f_i(x) = P(x - c_i)[i] */
@@ -325,6 +328,81 @@ int orc_stream(const int *dims, const double *prm, int halfway,
         }
     free(acc);
     free(Ph);
+    return 0;
+}
+
+/*
+ * Zoom-in with Effective Boundaries (Sec. 2.6) at the plane z = zs, fed from
+ * a virtual cylinder below it (directions with c_z = +1 are the unknowns).
+ *
+ * orc_zieb_inflow: the mean in-flowing velocity v_f, the z-velocity of the
+ * state P (u = (sum P c - F/2)/rho) averaged over the plane's fluid nodes;
+ * also their mean density.
+ *
+ * orc_zieb_density: eq. (ZIEBdesity8), the explicit update of the density in
+ * the virtual cylinder from the piston velocity vp, v_f, the piston area A
+ * and the remaining cylinder volume V0 - A Hp (time step 1).
+ *
+ * orc_zieb: applied to the streamed populations f of the plane's fluid nodes.
+ * The unknown directions were not received (orc_stream skips them), so they
+ * keep the node's own values P(x_S); with rho* the sum of the populations,
+ * f_12 becomes rho_next - (rho* - f_12) (eq. ZIEBdesity9), u = sum f c /
+ * rho_next, and every population is set to the equilibrium at (rho_next, u).
+ */
+int orc_zieb_inflow(const int *dims, const double *prm, const int32_t *own, const double *P, int zs,
+                    double *out)
+{
+    const int nx = dims[0], ny = dims[1];
+    const long N = (long)nx * ny * dims[2];
+    double su = 0.0, sr = 0.0;
+    long cnt = 0;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            long n = x + (long)nx * (y + (long)ny * zs);
+            if (own[n] >= 0) continue;
+            double r = 0.0, jz = 0.0;
+            for (int i = 0; i < Q19; ++i) {
+                r += P[(long)i * N + n];
+                jz += CZ[i] * P[(long)i * N + n];
+            }
+            su += (jz - 0.5 * prm[5]) / r;
+            sr += r;
+            ++cnt;
+        }
+    out[0] = cnt ? su / cnt : 0.0;
+    out[1] = cnt ? sr / cnt : 0.0;
+    return (int)cnt;
+}
+
+double orc_zieb_density(double rho, double vp, double vf, double area, double volume, double Hp)
+{
+    return rho * exp((vp * area - vf * area) / (volume - area * Hp));
+}
+
+int orc_zieb(const int *dims, int zs, double rho_next, const int32_t *own, const double *P, double *f)
+{
+    const int nx = dims[0], ny = dims[1];
+    const long N = (long)nx * ny * dims[2];
+    const int i12 = 12;  /* (0, 0, 1): streams into the domain normal to the interface */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            long n = x + (long)nx * (y + (long)ny * zs);
+            if (own[n] >= 0) continue;
+            for (int i = 0; i < Q19; ++i)
+                if (CZ[i] == 1) f[(long)i * N + n] = P[(long)i * N + n];
+            double rs = 0.0;
+            for (int i = 0; i < Q19; ++i) rs += f[(long)i * N + n];
+            f[(long)i12 * N + n] = rho_next - (rs - f[(long)i12 * N + n]);
+            double j[3] = {0.0, 0.0, 0.0};
+            for (int i = 0; i < Q19; ++i) {
+                j[0] += CX[i] * f[(long)i * N + n];
+                j[1] += CY[i] * f[(long)i * N + n];
+                j[2] += CZ[i] * f[(long)i * N + n];
+            }
+            double fe[Q19];
+            orc_equilibrium(rho_next, j[0] / rho_next, j[1] / rho_next, j[2] / rho_next, fe);
+            for (int i = 0; i < Q19; ++i) f[(long)i * N + n] = fe[i];
+        }
     return 0;
 }
 
