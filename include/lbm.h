@@ -220,6 +220,27 @@ lbm_status lbm_count_fluid(lbm_handle h, int64_t *n_fluid);
 lbm_status lbm_profile(lbm_handle h, int32_t enable);
 lbm_status lbm_profile_read(lbm_handle h, double *ms_total, int64_t *launches);
 
+/* Zoom-in with Effective Boundaries (Sec. 2.6): the plane z = z_s is fed
+ * by a removed cylinder of volume `volume` and piston area `area` whose
+ * piston moves at v_piston (lattice units, time step 1) towards +z.  The
+ * whole layer z_s - 1 (periodic) must be wall voxels; it stands for the
+ * removed domain, and the plane's links into it are not wall links.  Each
+ * step: the mean in-flowing velocity v_f of the plane's fluid nodes (u of the
+ * current state, as in lbm_get_macro) and eq. (ZIEBdesity8) give the
+ * cylinder's new density rho (at the first step rho starts from the plane's
+ * mean density); on the plane, the populations arriving from the removed
+ * domain keep the node's own values, f_12 becomes rho - (rho* - f_12) with
+ * rho* the node's density (eq. ZIEBdesity9), and all populations become the
+ * equilibrium at rho and u = sum f c / rho before the collision.  The piston
+ * displacement H advances by v_piston per step.  z_s < 0 removes the plane.
+ * Must be called after lbm_set_walls and before lbm_init_fields; handles
+ * with a plane cannot be batched.  lbm_get_zieb writes {rho, H, v_f} of the
+ * last step (host, 3 doubles; synchronises).  Errors: ARG (range, the layer
+ * below is not all wall), STATE (after lbm_init_fields, before the walls;
+ * no plane for lbm_get_zieb), HIP. */
+lbm_status lbm_set_zieb(lbm_handle h, int32_t z_s, double area, double volume, double v_piston);
+lbm_status lbm_get_zieb(lbm_handle h, double *state);
+
 /* Tile shape of the step kernel, the nodes of one 256-thread workgroup:
  * 0 = 64x2x2, 1 = 32x4x2, 2 = 32x2x4, 3 = 16x8x2 (x, y, z).  Results are the
  * same bit for bit for every shape; only the speed differs.  lbm_create

@@ -85,6 +85,8 @@ _sig = {
     "lbm_count_fluid": (ct.c_int, [_H, ct.POINTER(ct.c_int64)]),
     "lbm_profile": (ct.c_int, [_H, ct.c_int32]),
     "lbm_profile_read": (ct.c_int, [_H, _dp, ct.POINTER(ct.c_int64)]),
+    "lbm_set_zieb": (ct.c_int, [_H, ct.c_int32, ct.c_double, ct.c_double, ct.c_double]),
+    "lbm_get_zieb": (ct.c_int, [_H, _dp]),
     "lbm_set_tile": (ct.c_int, [_H, ct.c_int32]),
     "lbm_get_tile": (ct.c_int, [_H, ct.POINTER(ct.c_int32)]),
     "lbm_autotune_tile": (ct.c_int, [_H, ct.c_int32, ct.c_char_p, ct.POINTER(ct.c_int32), _dp]),
@@ -281,6 +283,17 @@ def lbm_profile_read(h):
     return ms.value, n.value
 
 
+def lbm_set_zieb(h, z_s, area, volume, v_piston) -> None:
+    _check(h, _L.lbm_set_zieb(h, int(z_s), float(area), float(volume), float(v_piston)))
+
+
+def lbm_get_zieb(h):
+    """(cylinder density, piston displacement, mean inflow velocity) of the last step."""
+    out = (ct.c_double * 3)()
+    _check(h, _L.lbm_get_zieb(h, out))
+    return tuple(out)
+
+
 TILE_SHAPES = ("64x2x2", "32x4x2", "32x2x4", "16x8x2")
 
 
@@ -440,6 +453,12 @@ class Lattice:
 
     def profile_read(self):
         return lbm_profile_read(self.h)
+
+    def set_zieb(self, z_s, area, volume, v_piston):
+        lbm_set_zieb(self.h, z_s, area, volume, v_piston)
+
+    def zieb_state(self):
+        return lbm_get_zieb(self.h)
 
     def set_tile(self, shape):
         lbm_set_tile(self.h, shape)

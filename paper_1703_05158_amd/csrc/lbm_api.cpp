@@ -49,6 +49,11 @@ struct lbm_ctx {
     double *wl_part = nullptr;
     int n_wblk = 0;
     int64_t wl_bytes = 0;
+    std::vector<uint8_t> wall_host;    // host copy of the wall map
+    // inflow plane fed by a virtual cylinder (Sec. 2.6); zieb_z < 0: none
+    int zieb_z = -1;
+    double zieb_area = 0.0, zieb_volume = 0.0, zieb_vp = 0.0;
+    double *zstate = nullptr;          // ZiebState on the device
     int *flag = nullptr;
     int *flag_host = nullptr;
     double *scratch = nullptr;         // 4N doubles, export/import staging (lazy)
@@ -152,7 +157,29 @@ StepArgs step_args(const lbm_ctx *h)
     a.flag = c.nan_guard_every > 0 ? h->flag : nullptr;
     a.src = h->pop[h->cur];
     a.dst = h->pop[1 - h->cur];
+    a.zieb_z = h->zieb_z;
+    a.zieb_state = h->zstate;
     return a;
+}
+
+ZiebArgs zieb_args(const lbm_ctx *h)
+{
+    ZiebArgs z{};
+    z.nx = h->cfg.nx;
+    z.ny = h->cfg.ny;
+    z.nz = h->cfg.nz;
+    z.N = h->N;
+    z.Ns = h->Ns;
+    z.z = h->zieb_z;
+    z.rho0 = (float)h->cfg.rho0;
+    z.fz = (float)h->cfg.body_force[2];
+    z.area = h->zieb_area;
+    z.volume = h->zieb_volume;
+    z.vp = h->zieb_vp;
+    z.own = h->own;
+    z.pop = h->pop[h->cur];
+    z.state = h->zstate;
+    return z;
 }
 
 LinkArgs link_args(const lbm_ctx *h)
@@ -335,6 +362,8 @@ lbm_status build_wall_links(lbm_ctx *h, const uint8_t *wall, int n_walls)
                     const size_t n = (size_t)x + (size_t)nx * (y + (size_t)ny * z);
                     if (wall[n]) continue;
                     for (int i = 1; i < kQ; ++i) {
+                        // links of the inflow plane into the removed domain are not walls
+                        if (z == h->zieb_z && dev::CZ[i] == 1) continue;
                         const size_t s = (size_t)wrap(x - dev::CX[i], nx) +
                                          (size_t)nx * (wrap(y - dev::CY[i], ny) + (size_t)ny * wrap(z - dev::CZ[i], nz));
                         const int w = wall[s];
@@ -417,6 +446,7 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         dalloc(h, &h->tab[1], sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->walls, sizeof(double) * kWallStride * std::max(c.max_walls, 1)) != hipSuccess ||
         dalloc(h, &h->acc, sizeof(double) * 6 * std::max(nbt, 1)) != hipSuccess ||
+        dalloc(h, &h->zstate, sizeof(ZiebState)) != hipSuccess ||
         dalloc(h, &h->flag, sizeof(int)) != hipSuccess)
         return bail(LBM_ERR_OOM);
     if (hipHostMalloc((void **)&h->pinned, sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
@@ -445,7 +475,7 @@ void lbm_destroy(lbm_handle h)
     }
     free_wall_links(h);
     void *dev[] = {h->pop[0], h->pop[1], h->own, h->wall_map, h->tab[0], h->tab[1],
-                   h->walls, h->acc, h->flag, h->scratch};
+                   h->walls, h->acc, h->flag, h->scratch, h->zstate};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (h->pinned) (void)hipHostFree(h->pinned);
@@ -485,6 +515,7 @@ lbm_status lbm_set_walls(lbm_handle h, const uint8_t *wall_id, int32_t n_walls, 
         }
     TRY(copy_sync(h, h->wall_map, wall_id, (size_t)h->N, hipMemcpyHostToDevice));
     TRY(copy_sync(h, h->walls, wt.data(), sizeof(double) * wt.size(), hipMemcpyHostToDevice));
+    h->wall_host.assign(wall_id, wall_id + h->N);
     TRY(build_wall_links(h, wall_id, n_walls));
     h->n_walls = n_walls;
     return rasterize_full(h);
@@ -573,6 +604,8 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *u)
     GeomArgs g = geom(h);
     HIP_TRY(h, launch_init_pop(h->cfg.storage, g, rho_dev, u_dev, h->stream));
     HIP_TRY(h, launch_zero(h->acc, 6 * (h->cfg.max_bodies + h->cfg.max_walls), h->stream));
+    const ZiebState z0{-1.0, 0.0, 0.0, 0.0};
+    HIP_TRY(h, hipMemcpyAsync(h->zstate, &z0, sizeof z0, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->initialized = true;
     h->steps_done = 0;
@@ -595,6 +628,7 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
         la.nb = h->nb_state;
         la.bodies = h->tab[h->ts];
         la.pop = h->pop[h->cur];
+        if (h->zieb_z >= 0) HIP_TRY(h, launch_zieb_update(c.storage, zieb_args(h), h->stream));
         HIP_TRY(h, launch_links(c.storage, la, h->stream));
         HIP_TRY(h, launch_wall_forces(la, h->stream));
         a.src = h->pop[h->cur];
@@ -727,7 +761,8 @@ lbm_status lbm_get_state(lbm_handle h, void *buf, size_t *bytes)
     const size_t tabb = sizeof(double) * kBodyStride * std::max(h->cfg.max_bodies, 1);
     const size_t wallb = sizeof(double) * kWallStride * std::max(h->cfg.max_walls, 1);
     const size_t accb = sizeof(double) * 6 * std::max(h->cfg.max_bodies + h->cfg.max_walls, 1);
-    const size_t need = sizeof(StateHeader) + popb + sizeof(uint16_t) * h->N + (size_t)h->N + 2 * tabb + wallb + accb;
+    const size_t need = sizeof(StateHeader) + popb + sizeof(uint16_t) * h->N + (size_t)h->N + 2 * tabb + wallb + accb +
+                        sizeof(ZiebState);
     if (!buf) {
         *bytes = need;
         return LBM_OK;
@@ -764,6 +799,8 @@ lbm_status lbm_get_state(lbm_handle h, void *buf, size_t *bytes)
     TRY(copy_sync(h, p, h->walls, wallb, hipMemcpyDeviceToHost));
     p += wallb;
     TRY(copy_sync(h, p, h->acc, accb, hipMemcpyDeviceToHost));
+    p += accb;
+    TRY(copy_sync(h, p, h->zstate, sizeof(ZiebState), hipMemcpyDeviceToHost));
     *bytes = need;
     return LBM_OK;
 }
@@ -775,7 +812,8 @@ lbm_status lbm_set_state(lbm_handle h, const void *buf, size_t bytes)
     const size_t tabb = sizeof(double) * kBodyStride * std::max(h->cfg.max_bodies, 1);
     const size_t wallb = sizeof(double) * kWallStride * std::max(h->cfg.max_walls, 1);
     const size_t accb = sizeof(double) * 6 * std::max(h->cfg.max_bodies + h->cfg.max_walls, 1);
-    const size_t need = sizeof(StateHeader) + popb + sizeof(uint16_t) * h->N + (size_t)h->N + 2 * tabb + wallb + accb;
+    const size_t need = sizeof(StateHeader) + popb + sizeof(uint16_t) * h->N + (size_t)h->N + 2 * tabb + wallb + accb +
+                        sizeof(ZiebState);
     if (bytes < need) return fail(h, LBM_ERR_ARG, "state of %zu bytes < %zu expected", bytes, need);
     StateHeader hd;
     memcpy(&hd, buf, sizeof hd);
@@ -789,6 +827,7 @@ lbm_status lbm_set_state(lbm_handle h, const void *buf, size_t bytes)
     TRY(copy_sync(h, h->own, p, sizeof(uint16_t) * h->N, hipMemcpyHostToDevice));
     p += sizeof(uint16_t) * h->N;
     TRY(copy_sync(h, h->wall_map, p, (size_t)h->N, hipMemcpyHostToDevice));
+    h->wall_host.assign(reinterpret_cast<const uint8_t *>(p), reinterpret_cast<const uint8_t *>(p) + h->N);
     TRY(build_wall_links(h, reinterpret_cast<const uint8_t *>(p), hd.n_walls));
     p += h->N;
     TRY(copy_sync(h, h->tab[h->ts], p, tabb, hipMemcpyHostToDevice));
@@ -798,6 +837,8 @@ lbm_status lbm_set_state(lbm_handle h, const void *buf, size_t bytes)
     TRY(copy_sync(h, h->walls, p, wallb, hipMemcpyHostToDevice));
     p += wallb;
     TRY(copy_sync(h, h->acc, p, accb, hipMemcpyHostToDevice));
+    p += accb;
+    TRY(copy_sync(h, h->zstate, p, sizeof(ZiebState), hipMemcpyHostToDevice));
     h->n_walls = hd.n_walls;
     h->nb_state = hd.nb_state;
     h->nb_next = hd.nb_next;
@@ -860,6 +901,44 @@ lbm_status lbm_profile_read(lbm_handle h, double *ms_total, int64_t *launches)
     return LBM_OK;
 }
 
+
+lbm_status lbm_set_zieb(lbm_handle h, int32_t z_s, double area, double volume, double v_piston)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (h->initialized) return fail(h, LBM_ERR_STATE, "the inflow plane must be set before lbm_init_fields");
+    const int nx = h->cfg.nx, ny = h->cfg.ny, nz = h->cfg.nz;
+    if (z_s < 0) {  // remove the plane
+        h->zieb_z = -1;
+        if (h->n_walls > 0 && !h->wall_host.empty()) return build_wall_links(h, h->wall_host.data(), h->n_walls);
+        return LBM_OK;
+    }
+    if (z_s >= nz) return fail(h, LBM_ERR_ARG, "z_s %d outside [0, %d)", z_s, nz);
+    if (!(area > 0.0) || !(volume > 0.0) || !std::isfinite(area) || !std::isfinite(volume) || !std::isfinite(v_piston))
+        return fail(h, LBM_ERR_ARG, "area and volume must be positive and finite, v_piston finite");
+    const int zv = (z_s + nz - 1) % nz;
+    if (h->wall_host.empty()) return fail(h, LBM_ERR_STATE, "set the walls first: layer z = %d must be wall", zv);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            if (!h->wall_host[(size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * zv)])
+                return fail(h, LBM_ERR_ARG, "node (%d, %d, %d) below the inflow plane is not a wall", x, y, zv);
+    h->zieb_z = z_s;
+    h->zieb_area = area;
+    h->zieb_volume = volume;
+    h->zieb_vp = v_piston;
+    return build_wall_links(h, h->wall_host.data(), h->n_walls);
+}
+
+lbm_status lbm_get_zieb(lbm_handle h, double *state)
+{
+    if (!h || !state) return h ? fail(h, LBM_ERR_ARG, "NULL output") : LBM_ERR_ARG;
+    if (h->zieb_z < 0) return fail(h, LBM_ERR_STATE, "no inflow plane");
+    ZiebState z{};
+    TRY(copy_sync(h, &z, h->zstate, sizeof z, hipMemcpyDeviceToHost));
+    state[0] = z.rho;
+    state[1] = z.H;
+    state[2] = z.vf;
+    return LBM_OK;
+}
 
 lbm_status lbm_set_tile(lbm_handle h, int32_t shape)
 {
@@ -1081,6 +1160,7 @@ lbm_status lbm_batch_create(const lbm_handle *members, int32_t n, void *stream, 
         if (h->dirty) return fail(h, LBM_ERR_STATE, "batch member %d: bodies set since the last step", i);
         if (h->cfg.storage != members[0]->cfg.storage)
             return fail(h, LBM_ERR_ARG, "batch member %d: storage differs from member 0", i);
+        if (h->zieb_z >= 0) return fail(h, LBM_ERR_ARG, "batch member %d has an inflow plane", i);
         for (int j = 0; j < i; ++j)
             if (members[j] == h) return fail(h, LBM_ERR_ARG, "batch member %d repeats member %d", i, j);
     }

@@ -42,6 +42,26 @@ struct StepArgs {
     const void *src;
     void *dst;
     int *flag;                    // NaN guard, may be null
+    int zieb_z;                   // z of the inflow plane fed by a virtual cylinder, -1 = none
+    const double *zieb_state;     // ZiebState: rho is the cylinder density of this step
+};
+
+// Zoom-in with Effective Boundaries (Sec. 2.6): the state of the virtual
+// cylinder below the plane z = z.
+struct ZiebState {
+    double rho;                   // cylinder density (< 0: take the plane's mean at the first step)
+    double H;                     // piston displacement
+    double vf;                    // mean inflow velocity used by the last update
+    double pad;
+};
+
+struct ZiebArgs {
+    int nx, ny, nz, N, Ns, z;
+    float rho0, fz;
+    double area, volume, vp;
+    const uint16_t *own;
+    const void *pop;              // current state
+    double *state;                // ZiebState
 };
 
 // Boundary-link pass: for every link from a fluid node x to a solid node
@@ -115,6 +135,8 @@ int batch_links_blocks_per_cu(int storage);
 hipError_t launch_batch_links(int storage, const BatchLinkArgs &b, int grid, hipStream_t s);
 hipError_t launch_batch_wall_forces(const BatchLinkArgs &b, hipStream_t s);
 hipError_t launch_batch_flip(int *cur, int n, hipStream_t s);
+
+hipError_t launch_zieb_update(int storage, const ZiebArgs &z, hipStream_t s);
 
 hipError_t launch_walls_init(const uint8_t *wall, uint16_t *own, int N, hipStream_t s);
 hipError_t launch_vacate(const GeomArgs &g, hipStream_t s);

@@ -35,6 +35,44 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks)
     return (b & 7) * per + (b >> 3);
 }
 
+// Inflow plane of a virtual cylinder (Sec. 2.6), on the streamed deviations
+// g of a plane node: the directions from the removed domain (c_z = +1) were
+// not received and keep the node's own values; with rho* the node's density,
+// f_12 becomes rho - (rho* - f_12) for the cylinder density rho of this step
+// (eq. ZIEBdesity9), u = sum f c / rho, and all populations are set to the
+// equilibrium at (rho, u).  The collision then follows as at every node.
+template <int S>
+__device__ __forceinline__ void zieb_plane(const StepArgs &a, const typename Store<S>::T *src, uint32_t idx,
+                                        float (&g)[kQ])
+{
+    using St = Store<S>;
+    const size_t Ns = (size_t)a.Ns;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i)
+        if (CZ[i] == 1) g[i] = St::ld(at(src + (size_t)i * Ns, idx));
+    const float rho = (float)a.zieb_state[0];
+    float rd = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) rd += g[i];
+    g[12] += rho - (a.rho0 + rd);  // deviations: f_12 - w_12 rho0 shifts by rho - rho*
+    float jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+        jx += CX[i] * g[i];
+        jy += CY[i] * g[i];
+        jz += CZ[i] * g[i];
+    }
+    const float ir = 1.0f / rho;
+    const float ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    const float uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const float w = (float)wgt(i);
+        const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+        g[i] = w * (rho - a.rho0) + w * rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+    }
+}
+
 // Tile t (TX x TY x TZ nodes, one per thread) of the lattice described by a.
 template <int S, int TX, int TY, int TZ>
 __device__ __forceinline__ void tile_step(const StepArgs &a, int t)
@@ -73,6 +111,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int t)
             const int sz = CZ[i] > 0 ? zm : (CZ[i] < 0 ? zp : z);
             g[i] = St::ld(at(src + (size_t)i * Ns, (uint32_t)(sx + nx * (sy + ny * sz))));
         }
+        if (z == a.zieb_z) zieb_plane<S>(a, src, idx, g);
     }
     {
         // moments in opposite pairs (i, i+9): even and odd parts
@@ -200,6 +239,61 @@ hipError_t launch_step_s(const StepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// The virtual cylinder's update of one step (one workgroup): the mean
+// in-flowing velocity v_f and density of the plane's fluid nodes from the
+// current state (u = (sum f c - F/2)/rho), then eq. (ZIEBdesity8) for the
+// cylinder density, which the plane takes in this step, and the piston
+// displacement.  Sums in FP64 in a fixed order.
+template <int S>
+__global__ __launch_bounds__(1024) void k_zieb_update(ZiebArgs z)
+{
+    using St = Store<S>;
+    const typename St::T *pop = static_cast<const typename St::T *>(z.pop);
+    __shared__ double s_red[3][16];
+    double su = 0.0, sr = 0.0, sc = 0.0;
+    const int plane = z.nx * z.ny;
+    for (int k = threadIdx.x; k < plane; k += blockDim.x) {
+        const uint32_t n = (uint32_t)(k + plane * z.z);
+        if (z.own[n] < kVacated) continue;
+        double rd = 0.0, jz = 0.0;
+        for (int i = 0; i < kQ; ++i) {
+            const double gi = (double)St::ld(pop + (size_t)i * z.Ns + n);
+            rd += gi;
+            jz += dcz(i) * gi;
+        }
+        const double r = (double)z.rho0 + rd;
+        su += (jz - 0.5 * (double)z.fz) / r;
+        sr += r;
+        sc += 1.0;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        su += __shfl_xor(su, off);
+        sr += __shfl_xor(sr, off);
+        sc += __shfl_xor(sc, off);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_red[0][wv] = su;
+        s_red[1][wv] = sr;
+        s_red[2][wv] = sc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tu = 0.0, tr = 0.0, tc = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            tu += s_red[0][w];
+            tr += s_red[1][w];
+            tc += s_red[2][w];
+        }
+        const double vf = tc > 0.0 ? tu / tc : 0.0;
+        double *st = z.state;
+        const double rho = st[0] < 0.0 ? (tc > 0.0 ? tr / tc : (double)z.rho0) : st[0];
+        st[0] = rho * exp((z.vp * z.area - vf * z.area) / (z.volume - z.area * st[1]));
+        st[1] += z.vp;
+        st[2] = vf;
+    }
+}
+
 // The batched step kernel for a storage type and tile shape.
 template <int S>
 const void *batch_step_kernel_s(int shape)
@@ -241,6 +335,17 @@ hipError_t launch_batch_step(int storage, int shape, const BatchStepArgs &b, int
     BatchStepArgs arg = b;
     void *args[] = {&arg};
     return hipLaunchKernel(k, dim3(grid), dim3(kBlock), args, 0, s);
+}
+
+hipError_t launch_zieb_update(int storage, const ZiebArgs &z, hipStream_t s)
+{
+    switch (storage) {
+    case 0: hipLaunchKernelGGL(k_zieb_update<0>, dim3(1), dim3(1024), 0, s, z); break;
+    case 1: hipLaunchKernelGGL(k_zieb_update<1>, dim3(1), dim3(1024), 0, s, z); break;
+    case 2: hipLaunchKernelGGL(k_zieb_update<2>, dim3(1), dim3(1024), 0, s, z); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t s)

@@ -1,0 +1,97 @@
+"""The inflow plane fed by a virtual cylinder (Sec. 2.6) on the GPU, against
+the FP64 oracle: a duct closed at its far end, with spheres, compressed by
+the virtual piston through the plane z = 1.  Same bars as the step itself
+(populations 1e-5 relative, forces 1e-4 norm-relative); the cylinder state
+to 1e-6; checkpoints carry the cylinder state.
+"""
+import numpy as np
+import pytest
+
+import lbm_workloads as W
+from ._pair import force_rel_err, pop_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _case():
+    nx, ny, nz = 24, 20, 48
+    w = np.zeros((nz, ny, nx), np.uint8)
+    w[:, :, 0] = w[:, :, nx - 1] = 1
+    w[:, 0, :] = w[:, ny - 1, :] = 1
+    w[0] = 1            # stands for the removed domain below the plane z = 1
+    w[nz - 1] = 1       # closed far end
+    rng = np.random.Generator(np.random.PCG64(31))
+    R = np.array([3.0, 2.5, 3.5])
+    X = W.rsa_pack(rng, R, (2, 2, 6), (nx - 2, ny - 2, nz - 4), gap=1.0, box=(nx, ny, nz),
+                   periodic=(False, False, False))
+    u = rng.normal(0.0, 0.005, size=(3, nz, ny, nx))
+    case = W.Case(name="zieb_duct", nx=nx, ny=ny, nz=nz, tau0=0.7, smag_c=0.1, wall_id=w,
+                  wall_vel=np.zeros((1, 3)), wall_ref=np.zeros((1, 3)), X=X, V=np.zeros((3, 3)),
+                  Omega=np.zeros((3, 3)), R=R, u_init=u)
+    fluid_plane = float((w[1] == 0).sum())
+    volume = 2.0 * float((w == 0).sum())
+    return case, (1, fluid_plane, volume, 0.01)
+
+
+def _pair(torch_stream, storage="f32"):
+    import oracle
+    from paper_1703_05158_amd import Lattice
+    case, zp = _case()
+    o = oracle.Oracle.from_case(case, init=False)
+    o.set_zieb(*zp)
+    o.init_fields(case.rho_init, case.u_init)
+    lat = Lattice.from_case(case, storage=storage, stream=torch_stream, init=False)
+    lat.set_zieb(*zp)
+    lat.init_fields(case.rho_init, case.u_init)
+    return o, lat, case, zp
+
+
+def test_zieb_parity(torch_stream):
+    o, lat, case, _ = _pair(torch_stream)
+    for n in range(60):
+        o.step(1)
+        lat.step(1)
+    pe = pop_rel_err(o, lat)
+    fe, te = force_rel_err(o, lat)
+    rho, H, vf = lat.zieb_state()
+    print(f"pop {pe:.2e} F {fe:.2e} T {te:.2e} rho {rho:.8f} (oracle {o.zieb['rho']:.8f}) vf {vf:.3e}")
+    assert pe <= 1e-5 and fe <= 1e-4 and te <= 1e-4
+    assert rho == pytest.approx(o.zieb["rho"], rel=1e-6)
+    assert H == pytest.approx(o.zieb["H"], rel=1e-12)
+    assert vf == pytest.approx(o.zieb["vf"], abs=1e-7)
+    assert rho > 1.0           # the piston has compressed the cylinder
+    lat.close()
+
+
+def test_zieb_checkpoint_resume(torch_stream):
+    from paper_1703_05158_amd import Lattice
+    _, lat, case, zp = _pair(torch_stream)
+    lat.step(20)
+    state = lat.get_state()
+    lat.step(15)
+    P_ref, z_ref = lat.get_populations(), lat.zieb_state()
+    lat2 = Lattice.from_case(case, stream=torch_stream, init=False)
+    lat2.set_zieb(*zp)
+    lat2.set_state(state)
+    lat2.step(15)
+    assert np.array_equal(lat2.get_populations(), P_ref)
+    assert lat2.zieb_state() == z_ref
+    lat.close()
+    lat2.close()
+
+
+def test_zieb_rejects_bad_planes(torch_stream):
+    from paper_1703_05158_amd import Batch, LBMError, Lattice
+    case, (z, a, v, vp) = _case()
+    lat = Lattice.from_case(case, stream=torch_stream, init=False)
+    with pytest.raises(LBMError):
+        lat.set_zieb(5, a, v, vp)       # the layer below z = 5 is not all wall
+    with pytest.raises(LBMError):
+        lat.set_zieb(z, -1.0, v, vp)
+    lat.set_zieb(z, a, v, vp)
+    lat.init_fields()
+    with pytest.raises(LBMError):
+        lat.set_zieb(z, a, v, vp)       # after lbm_init_fields
+    with pytest.raises(LBMError):
+        Batch([lat])
+    lat.close()
