@@ -241,6 +241,28 @@ lbm_status lbm_profile_read(lbm_handle h, double *ms_total, int64_t *launches);
 lbm_status lbm_set_zieb(lbm_handle h, int32_t z_s, double area, double volume, double v_piston);
 lbm_status lbm_get_zieb(lbm_handle h, double *state);
 
+/* Replace the body force (Guo source density per fluid node, Sec. 2.2 with
+ * the forcing reading) for the following steps.  Errors: ARG. */
+lbm_status lbm_set_body_force(lbm_handle h, const double *F);
+
+/* Gradient of the summed sphere drag.  J = sum_b F_b,x, the x-component of
+ * the momentum-exchange force on every sphere (Sec. 2.3) at the last of
+ * nsteps steps from the current state, with the spheres held where they are
+ * (their velocities V enter only the moving-boundary term).  The call runs
+ * the nsteps steps (the handle's state advances as with lbm_step, and the
+ * forces of the last step stay readable), keeping every ckpt-th state, then
+ * runs the reverse-mode kernels backwards, recomputing each stretch of ckpt
+ * steps from its checkpoint: the transposed collision per node, the
+ * transposed streaming and the transposed boundary links.  Outputs (host):
+ * J; dJdF[3] = dJ/d(body force); dJdV[3 n_bodies] = dJ/dV_b, sphere-major
+ * (may be NULL with no spheres).  The square root of Q = Pi:Pi has the
+ * derivative 1/(2 sqrt(Q + 1e-30)).  Device memory: ceil(nsteps/ckpt) +
+ * min(ckpt, nsteps) + 3 population buffers, allocated for the call.  Needs
+ * FP32 storage, no walls and no inflow plane.  Synchronises.  Errors: ARG,
+ * STATE, OOM, HIP. */
+lbm_status lbm_drag_gradient(lbm_handle h, int32_t nsteps, int32_t ckpt, double *J, double *dJdF,
+                             double *dJdV);
+
 /* Tile shape of the step kernel, the nodes of one 256-thread workgroup:
  * 0 = 64x2x2, 1 = 32x4x2, 2 = 32x2x4, 3 = 16x8x2 (x, y, z).  Results are the
  * same bit for bit for every shape; only the speed differs.  lbm_create

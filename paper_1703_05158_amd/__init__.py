@@ -18,7 +18,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "LBMError", "LBMConfig", "LBMInfo", "config", "Lattice", "Batch", "TILE_SHAPES",
+    "LBMError", "LBMConfig", "LBMInfo", "config", "Lattice", "Batch", "TILE_SHAPES", "SphereDrag",
     "lbm_version", "lbm_create", "lbm_destroy", "lbm_last_error", "lbm_set_stream",
     "lbm_set_walls", "lbm_set_bodies", "lbm_set_bodies_device", "lbm_init_fields",
     "lbm_step", "lbm_get_forces", "lbm_get_forces_device", "lbm_get_populations",
@@ -87,6 +87,8 @@ _sig = {
     "lbm_profile_read": (ct.c_int, [_H, _dp, ct.POINTER(ct.c_int64)]),
     "lbm_set_zieb": (ct.c_int, [_H, ct.c_int32, ct.c_double, ct.c_double, ct.c_double]),
     "lbm_get_zieb": (ct.c_int, [_H, _dp]),
+    "lbm_set_body_force": (ct.c_int, [_H, ct.c_void_p]),
+    "lbm_drag_gradient": (ct.c_int, [_H, ct.c_int32, ct.c_int32, _dp, ct.c_void_p, ct.c_void_p]),
     "lbm_set_tile": (ct.c_int, [_H, ct.c_int32]),
     "lbm_get_tile": (ct.c_int, [_H, ct.POINTER(ct.c_int32)]),
     "lbm_autotune_tile": (ct.c_int, [_H, ct.c_int32, ct.c_char_p, ct.POINTER(ct.c_int32), _dp]),
@@ -294,6 +296,19 @@ def lbm_get_zieb(h):
     return tuple(out)
 
 
+def lbm_set_body_force(h, F) -> None:
+    _check(h, _L.lbm_set_body_force(h, _ptr(_host(F, np.float64, 3))))
+
+
+def lbm_drag_gradient(h, nsteps, ckpt, n_bodies):
+    """(J, dJ/dF [3], dJ/dV [n_bodies, 3])."""
+    J = ct.c_double(0.0)
+    dF = np.zeros(3)
+    dV = np.zeros((max(n_bodies, 1), 3))
+    _check(h, _L.lbm_drag_gradient(h, int(nsteps), int(ckpt), ct.byref(J), _ptr(dF), _ptr(dV)))
+    return J.value, dF, dV[:n_bodies]
+
+
 TILE_SHAPES = ("64x2x2", "32x4x2", "32x2x4", "16x8x2")
 
 
@@ -460,6 +475,12 @@ class Lattice:
     def zieb_state(self):
         return lbm_get_zieb(self.h)
 
+    def set_body_force(self, F):
+        lbm_set_body_force(self.h, F)
+
+    def drag_gradient(self, nsteps, ckpt):
+        return lbm_drag_gradient(self.h, nsteps, ckpt, self.info()["n_bodies"])
+
     def set_tile(self, shape):
         lbm_set_tile(self.h, shape)
 
@@ -501,3 +522,41 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class SphereDrag:
+    """J = sum_b F_b,x after `nsteps` steps from a fixed start state, as a
+    torch function of the body force F (3,) and the sphere velocities
+    V (n_bodies, 3); its backward pass is the library's reverse-mode kernels
+    (lbm_drag_gradient).  Positions, angular velocities and radii stay
+    those given; every evaluation restarts from `start_state` (a checkpoint
+    from Lattice.get_state)."""
+
+    def __init__(self, lattice, start_state, X, Omega, R, nsteps, ckpt):
+        import torch
+
+        self.lat, self.state = lattice, start_state
+        self.X, self.Omega, self.R = np.asarray(X), np.asarray(Omega), np.asarray(R)
+        self.nsteps, self.ckpt = int(nsteps), int(ckpt)
+        outer = self
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, F, V):
+                outer.lat.set_state(outer.state)
+                outer.lat.set_body_force(F.detach().cpu().double().numpy())
+                outer.lat.set_bodies(outer.X, V.detach().cpu().double().numpy(), outer.Omega, outer.R)
+                J, dF, dV = outer.lat.drag_gradient(outer.nsteps, outer.ckpt)
+                ctx.save_for_backward(torch.as_tensor(dF, dtype=F.dtype, device=F.device),
+                                      torch.as_tensor(dV, dtype=V.dtype, device=V.device))
+                return torch.tensor(J, dtype=F.dtype, device=F.device)
+
+            @staticmethod
+            def backward(ctx, gJ):
+                dF, dV = ctx.saved_tensors
+                return gJ * dF, gJ * dV
+
+        self._fn = _Fn
+
+    def __call__(self, F, V):
+        return self._fn.apply(F, V)

@@ -940,6 +940,125 @@ lbm_status lbm_get_zieb(lbm_handle h, double *state)
     return LBM_OK;
 }
 
+lbm_status lbm_set_body_force(lbm_handle h, const double *F)
+{
+    if (!h || !F) return h ? fail(h, LBM_ERR_ARG, "NULL force") : LBM_ERR_ARG;
+    if (!finite_all(F, 3)) return fail(h, LBM_ERR_ARG, "non-finite body force");
+    for (int a = 0; a < 3; ++a) h->cfg.body_force[a] = F[a];
+    return LBM_OK;
+}
+
+lbm_status lbm_drag_gradient(lbm_handle h, int32_t nsteps, int32_t ckpt, double *J, double *dJdF, double *dJdV)
+{
+    if (!h) return LBM_ERR_ARG;
+    TRY(check_ready(h));
+    if (nsteps < 1 || ckpt < 1) return fail(h, LBM_ERR_ARG, "nsteps and ckpt must be at least 1");
+    if (!J || !dJdF || (h->nb_next > 0 && !dJdV)) return fail(h, LBM_ERR_ARG, "NULL output");
+    if (h->cfg.storage != 0) return fail(h, LBM_ERR_ARG, "the drag gradient needs FP32 storage");
+    if (h->n_walls > 0) return fail(h, LBM_ERR_ARG, "the drag gradient has no wall links");
+    if (h->zieb_z >= 0) return fail(h, LBM_ERR_ARG, "the drag gradient has no inflow plane");
+    if (h->dirty) TRY(rasterize_update(h));
+    const int nb = h->nb_state;
+    const size_t popb = sizeof(float) * kQ * (size_t)h->Ns;
+    const int nck = (nsteps + ckpt - 1) / ckpt;
+    const int nseg = std::min(ckpt, nsteps);
+    // device buffers of this call
+    std::vector<void *> bufs;
+    auto get = [&](size_t bytes) -> void * {
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) return nullptr;
+        bufs.push_back(p);
+        return p;
+    };
+    auto release = [&]() {
+        (void)hipStreamSynchronize(h->stream);
+        for (void *p : bufs) (void)hipFree(p);
+        bufs.clear();
+    };
+    std::vector<float *> ck((size_t)nck), seg((size_t)nseg);
+    for (auto &b : ck) b = static_cast<float *>(get(popb));
+    for (auto &b : seg) b = static_cast<float *>(get(popb));
+    float *lam[2] = {static_cast<float *>(get(popb)), static_cast<float *>(get(popb))};
+    float *mu = static_cast<float *>(get(popb));
+    const int nbt = std::max(nb + h->n_walls, 1);
+    double *fscratch = static_cast<double *>(get(sizeof(double) * 6 * (size_t)nbt));
+    double *accsave = static_cast<double *>(get(sizeof(double) * 6 * (size_t)nbt));
+    double *dF_tile = static_cast<double *>(get(sizeof(double) * 3 * (size_t)h->n_tiles));
+    double *dF = static_cast<double *>(get(sizeof(double) * 3));
+    double *dV = static_cast<double *>(get(sizeof(double) * 3 * (size_t)std::max(nb, 1)));
+    for (void *p : bufs)
+        if (!p) {
+            release();
+            return fail(h, LBM_ERR_OOM, "no device memory for %d checkpoints and %d recomputed states", nck, nseg);
+        }
+    const lbm_config &c = h->cfg;
+    // forward, keeping every ckpt-th state
+    for (int n = 0; n < nsteps; ++n) {
+        if (n % ckpt == 0) HIP_TRY(h, hipMemcpyAsync(ck[(size_t)(n / ckpt)], h->pop[h->cur], popb, hipMemcpyDeviceToDevice, h->stream));
+        LinkArgs la = link_args(h);
+        HIP_TRY(h, launch_links(c.storage, la, h->stream));
+        StepArgs a = step_args(h);
+        a.flag = nullptr;
+        HIP_TRY(h, launch_step(c.storage, a, h->stream));
+        h->cur = 1 - h->cur;
+        h->steps_done++;
+    }
+    std::vector<double> acc_h((size_t)6 * nbt);
+    TRY(copy_sync(h, acc_h.data(), h->acc, sizeof(double) * 6 * nbt, hipMemcpyDeviceToHost));
+    double Jv = 0.0;
+    for (int b = 0; b < nb; ++b) Jv += acc_h[(size_t)6 * b];
+    HIP_TRY(h, hipMemcpyAsync(accsave, h->acc, sizeof(double) * 6 * nbt, hipMemcpyDeviceToDevice, h->stream));
+    // backward: the objective's derivative gives the adjoint of P_{N-1}
+    HIP_TRY(h, hipMemsetAsync(dF_tile, 0, sizeof(double) * 3 * h->n_tiles, h->stream));
+    HIP_TRY(h, hipMemsetAsync(dV, 0, sizeof(double) * 3 * std::max(nb, 1), h->stream));
+    HIP_TRY(h, hipMemsetAsync(lam[0], 0, popb, h->stream));
+    LinkArgs lg = link_args(h);
+    lg.out = fscratch;
+    AdjLinkArgs al{lg, nullptr, lam[0], dV};
+    HIP_TRY(h, launch_adj_links(al, h->stream));
+    int li = 0;  // lam[li] is the adjoint of P_m
+    for (int s = nck - 1; s >= 0; --s) {
+        const int start = s * ckpt, end = std::min(start + ckpt, nsteps);
+        // recompute P_start .. P_{end-1} of the segment
+        HIP_TRY(h, hipMemcpyAsync(seg[0], ck[(size_t)s], popb, hipMemcpyDeviceToDevice, h->stream));
+        for (int k = start + 1; k < end; ++k) {
+            LinkArgs la = link_args(h);
+            la.pop = seg[(size_t)(k - 1 - start)];
+            la.out = fscratch;
+            HIP_TRY(h, launch_links(c.storage, la, h->stream));
+            StepArgs a = step_args(h);
+            a.flag = nullptr;
+            a.src = seg[(size_t)(k - 1 - start)];
+            a.dst = seg[(size_t)(k - start)];
+            HIP_TRY(h, launch_step(c.storage, a, h->stream));
+        }
+        // steps m = k + 1 whose source P_k lies in the segment, m from N - 1 down
+        for (int m = std::min(end, nsteps - 1); m >= start + 1; --m) {
+            float *src = seg[(size_t)(m - 1 - start)];
+            LinkArgs la = link_args(h);
+            la.pop = src;
+            la.out = fscratch;
+            HIP_TRY(h, launch_links(c.storage, la, h->stream));  // link values of step m in src
+            StepArgs a = step_args(h);
+            a.flag = nullptr;
+            a.src = src;
+            AdjStepArgs ga{a, lam[li], mu, dF_tile};
+            HIP_TRY(h, launch_adj_collide(ga, h->stream));
+            HIP_TRY(h, launch_adj_stream(a, mu, lam[1 - li], h->stream));
+            AdjLinkArgs am{lg, mu, lam[1 - li], dV};
+            HIP_TRY(h, launch_adj_links(am, h->stream));
+            li = 1 - li;
+        }
+    }
+    HIP_TRY(h, launch_adj_reduce(dF_tile, h->n_tiles, dF, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(h->acc, accsave, sizeof(double) * 6 * nbt, hipMemcpyDeviceToDevice, h->stream));
+    TRY(copy_sync(h, dJdF, dF, sizeof(double) * 3, hipMemcpyDeviceToHost));
+    if (nb > 0) TRY(copy_sync(h, dJdV, dV, sizeof(double) * 3 * nb, hipMemcpyDeviceToHost));
+    *J = Jv;
+    release();
+    return LBM_OK;
+}
+
 lbm_status lbm_set_tile(lbm_handle h, int32_t shape)
 {
     if (!h) return LBM_ERR_ARG;

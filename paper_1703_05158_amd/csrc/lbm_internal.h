@@ -111,6 +111,22 @@ struct BatchLinkArgs {
     int total_walls;
 };
 
+// Reverse-mode step for the gradient of the summed sphere drag (FP32
+// storage, fixed spheres, no walls).
+struct AdjStepArgs {
+    StepArgs a;                   // src = the state P_{n-1} the step starts from
+    const float *lam;             // adjoint of the post-collision state P_n, [19][Ns]
+    float *mu;                    // adjoint of the streamed populations f_n, [19][Ns]
+    double *dF_tile;              // [n_tiles][3], accumulated over the steps
+};
+
+struct AdjLinkArgs {
+    LinkArgs a;                   // geometry and bodies; pop unused
+    const float *mu;              // adjoint of f_n, or null: the objective's own derivative
+    float *lam;                   // adjoint of P_{n-1}, links add into it
+    double *dV;                   // [nb][3], accumulated over the steps
+};
+
 struct GeomArgs {
     int nx, ny, nz;
     int N;
@@ -137,6 +153,10 @@ hipError_t launch_batch_wall_forces(const BatchLinkArgs &b, hipStream_t s);
 hipError_t launch_batch_flip(int *cur, int n, hipStream_t s);
 
 hipError_t launch_zieb_update(int storage, const ZiebArgs &z, hipStream_t s);
+hipError_t launch_adj_collide(const AdjStepArgs &g, hipStream_t s);
+hipError_t launch_adj_stream(const StepArgs &a, const float *mu, float *lam, hipStream_t s);
+hipError_t launch_adj_links(const AdjLinkArgs &g, hipStream_t s);
+hipError_t launch_adj_reduce(const double *dF_tile, int n_tiles, double *dF, hipStream_t s);
 
 hipError_t launch_walls_init(const uint8_t *wall, uint16_t *own, int N, hipStream_t s);
 hipError_t launch_vacate(const GeomArgs &g, hipStream_t s);

@@ -415,6 +415,117 @@ __global__ __launch_bounds__(64) void k_wall_forces(LinkArgs a)
     if (lane < 6) a.out[6 * (a.nb + w) + lane] = v[lane];
 }
 
+// ---- reverse mode of the link pass ---------------------------------------
+//
+// Transpose of the boundary links for the gradient of the summed sphere
+// drag, with the spheres fixed and the same candidate enumeration and FP32
+// q as the forward pass.  A link (p, I) of sphere b from the fluid node
+// x = p + c_I wrote f_I(x) = a_k P(x)[K] + a_b P(x - c_K)[K] + a_i P(x)[I]
+// + a_w w_K rho0 c_I . u_w(V_b), with (a_k, a_b, a_i, a_w) = (2q, 1 - 2q, 0, 6)
+// for q < 1/2 with a fluid node behind x, (1, 0, 0, 6) without, and
+// (1/(2q), 0, 1 - 1/(2q), 3/q) for q >= 1/2.  Given the adjoint
+// m of f_I(x) (mu), the link adds a_k m, a_b m and a_i m to the adjoints of
+// those three populations and a_w w_K rho0 c_I m to dJ/dV_b.  Without mu the
+// weight is that of the objective itself, J = sum_b F_b,x with F_b = sum
+// (P(x)[K] + f_I(x)) c_K: m = c_K,x, plus c_K,x on P(x)[K] directly.
+// Several links can reach one population (thin gaps), so the adds are atomic.
+__device__ __forceinline__ void adj_sphere_block(const AdjLinkArgs &g, int b, SphereLds &L, double (*s_red)[6])
+{
+    const LinkArgs &a = g.a;
+    const double *B = a.bodies + (size_t)b * kBodyStride;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const size_t Ns = (size_t)a.Ns;
+    const int tid = threadIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (body_ok(B, nx, ny, nz)) {
+        const Box bx = body_box(B, 0);
+        const int total = bx.ex * bx.ey * bx.ez;
+        const uint16_t own_b = (uint16_t)(a.n_walls + b);
+        SphereK k;
+        k.X0 = B[0];
+        k.X1 = B[1];
+        k.X2 = B[2];
+        k.R2 = (float)(B[9] * B[9]);
+        const float mg = 0.01f + 1e-5f * k.R2;
+        const float ri = (float)B[9] - 1.5f;
+        const float in2 = ri > 0.0f ? ri * ri - mg : -1.0f;
+        for (int base = 0; base < total; base += kRoundNodes) {
+            __syncthreads();
+            const int kk = base + tid;
+            int px = 0, py = 0, pz = 0, tot;
+            uint32_t lm = 0;
+            if (tid < kRoundNodes && kk < total) lm = candidates(a, bx, k, mg, in2, kk, px, py, pz);
+            int pos = block_scan(__popc(lm), L.wtot, tot);
+            while (lm) {
+                const int I = __builtin_ctz(lm);
+                lm &= lm - 1;
+                L.item[pos++] = ((uint32_t)kk << 5) | (uint32_t)I;
+            }
+            __syncthreads();
+            for (int j = tid; j < tot; j += kBlock) {
+                const uint32_t it = L.item[j];
+                const int kj = (int)(it >> 5), I = (int)(it & 31), K = opp(I);
+                px = wrap1(bx.x0 + kj % bx.ex, nx);
+                py = wrap1(bx.y0 + (kj / bx.ex) % bx.ey, ny);
+                pz = wrap1(bx.z0 + kj / (bx.ex * bx.ey), nz);
+                const int cx = dcx(I), cy = dcy(I), cz = dcz(I);
+                const int x = wrap1(px + cx, nx), y = wrap1(py + cy, ny), z = wrap1(pz + cz, nz);
+                const uint32_t pi = (uint32_t)(px + nx * (py + ny * pz));
+                const uint32_t xi = (uint32_t)(x + nx * (y + ny * z));
+                if (*at(a.own, pi) != own_b || *at(a.own, xi) < kVacated) continue;
+                float q = 0.5f;
+                if (!a.halfway) {
+                    const float e0 = (float)min_image((double)x - k.X0, nx);
+                    const float e1 = (float)min_image((double)y - k.X1, ny);
+                    const float e2 = (float)min_image((double)z - k.X2, nz);
+                    const float bb = -(e0 * cx + e1 * cy + e2 * cz);
+                    const float aa = (float)(cx * cx + cy * cy + cz * cz);
+                    const float cc = (e0 * e0 + e1 * e1 + e2 * e2) - k.R2;
+                    const float disc = fmaxf(bb * bb - aa * cc, 0.0f);
+                    q = fminf(fmaxf(cc / (__builtin_sqrtf(disc) - bb), 0.0f), 1.0f);
+                }
+                const float ckx = (float)(-cx);
+                const float m = g.mu ? *at(g.mu + (size_t)I * Ns, xi) : ckx;
+                float ak, ab = 0.f, ai = 0.f, aw;
+                uint32_t bi = 0;
+                if (q < 0.5f) {
+                    bi = (uint32_t)(wrap1(x + cx, nx) + nx * (wrap1(y + cy, ny) + ny * wrap1(z + cz, nz)));
+                    if (*at(a.own, bi) >= kVacated) {
+                        ak = 2.0f * q;
+                        ab = 1.0f - 2.0f * q;
+                    } else {
+                        ak = 1.0f;
+                    }
+                    aw = 6.0f;
+                } else {
+                    const float h = 0.5f / q;
+                    ak = h;
+                    ai = 1.0f - h;
+                    aw = 3.0f / q;
+                }
+                atomicAdd(at(g.lam + (size_t)K * Ns, xi), ak * m + (g.mu ? 0.0f : ckx));
+                if (ab != 0.0f) atomicAdd(at(g.lam + (size_t)K * Ns, bi), ab * m);
+                if (ai != 0.0f) atomicAdd(at(g.lam + (size_t)I * Ns, xi), ai * m);
+                const double wv = (double)(aw * (float)wgt(K) * a.rho0 * m);
+                acc[0] += wv * cx;
+                acc[1] += wv * cy;
+                acc[2] += wv * cz;
+            }
+        }
+    }
+    block_sum<3>(acc, s_red);
+    if (tid == 0)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g.dV[3 * (size_t)b + c] += acc[c];
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_links(AdjLinkArgs g)
+{
+    __shared__ SphereLds L;
+    __shared__ double s_red[kWaves][6];
+    adj_sphere_block(g, blockIdx.x, L, s_red);
+}
+
 // Largest m with key(m) <= g over the members of a batch.
 template <typename F>
 __device__ __forceinline__ int find_member(int n, int g, F key)
@@ -515,6 +626,13 @@ hipError_t launch_batch_wall_forces(const BatchLinkArgs &b, hipStream_t s)
 hipError_t launch_batch_flip(int *cur, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_batch_flip, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, cur, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_links(const AdjLinkArgs &g, hipStream_t s)
+{
+    if (g.a.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_links, dim3(g.a.nb), dim3(kBlock), 0, s, g);
     return hipGetLastError();
 }
 

@@ -294,6 +294,228 @@ __global__ __launch_bounds__(1024) void k_zieb_update(ZiebArgs z)
     }
 }
 
+// ---- reverse mode (gradient of the summed sphere drag) ------------------
+//
+// For a step P_n = C(f_n), f_n = S(P_{n-1}), k_adj_collide turns the adjoint
+// lambda_n of P_n into the adjoint mu_n of the streamed populations f_n,
+// mu = (dC/df)^T lambda, node by node, and adds lambda . dC/dF (the body
+// force) to per-tile sums; k_adj_stream and the link kernel then apply the
+// transpose of the streaming S.  The collision is recomputed from f_n:
+// moments, the equilibrium, Pi, Q = Pi:Pi, tau* and the Guo source, as in
+// the forward step (Sec. 2.2); the derivative of sqrt(Q) is taken as
+// 1/(2 sqrt(Q + 1e-30)), finite where Q = 0.
+
+// mu = (dC/df)^T lam at one node (deviations g = f - w rho0), and the body-
+// force part added to Fb.
+__device__ __forceinline__ void collide_adjoint(const StepArgs &a, const float (&g)[kQ], const float (&lam)[kQ],
+                                                float (&mu)[kQ], double (&Fb)[3])
+{
+    const float F[3] = {a.fx, a.fy, a.fz};
+    float rd = 0.f, j[3] = {0.f, 0.f, 0.f}, S[3][3] = {{0.f}};
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int c[3] = {CX[i], CY[i], CZ[i]};
+        rd += g[i];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            j[p] += c[p] * g[i];
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (c[p] * c[q]) S[p][q] += c[p] * c[q] * g[i];
+        }
+    }
+    const float rho = a.rho0 + rd, ir = 1.0f / rho;
+    float u[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) u[p] = (j[p] + 0.5f * F[p]) * ir;
+    const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const float uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    float Pi[3][3], Q = 0.f;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            Pi[p][q] = S[p][q] - (p == q ? rd * (1.0f / 3.0f) : 0.f) - rho * u[p] * u[q];
+            Q += Pi[p][q] * Pi[p][q];
+        }
+    const float s = sqrtf(Q);
+    const float Rr = a.tau0 * a.tau0 + a.smag_k * s * ir, sR = sqrtf(Rr);
+    const float om = 2.0f / (a.tau0 + sR);
+    // adjoints of omega and of the equilibrium / source terms
+    float Ob = 0.f;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const float w = (float)wgt(i);
+        const float cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
+        const float cF = CX[i] * F[0] + CY[i] * F[1] + CZ[i] * F[2];
+        const float geq = w * (rd + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+        const float src = w * (3.0f * (cF - uF) + 9.0f * cu * cF);
+        Ob += lam[i] * (-(g[i] - geq) - 0.5f * src);
+    }
+    const float tb = -Ob * om * om;
+    const float Rb = tb * 0.25f / sR;
+    float rhob = -Rb * a.smag_k * s * ir * ir;
+    const float Qb = Rb * a.smag_k * ir * 0.5f / sqrtf(Q + 1e-30f);
+    float Pb[3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) Pb[p][q] = 2.0f * Pi[p][q] * Qb;
+    float rdb = -(Pb[0][0] + Pb[1][1] + Pb[2][2]) * (1.0f / 3.0f);
+    float ub[3] = {0.f, 0.f, 0.f};
+    double fb[3] = {0.0, 0.0, 0.0};
+    const float cs = 1.0f - 0.5f * om;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int c[3] = {CX[i], CY[i], CZ[i]};
+        const float w = (float)wgt(i);
+        const float cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+        const float cF = c[0] * F[0] + c[1] * F[1] + c[2] * F[2];
+        const float gq = om * lam[i] * w;   // adjoint of geq_i, times w_i
+        const float sq = cs * lam[i] * w;   // adjoint of the source S_i, times w_i
+        rdb += gq;
+        rhob += gq * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            ub[p] += gq * rho * (3.0f * c[p] + 9.0f * cu * c[p] - 3.0f * u[p]) + sq * (-3.0f * F[p] + 9.0f * c[p] * cF);
+            fb[p] += (double)(sq * (3.0f * (c[p] - u[p]) + 9.0f * cu * c[p]));
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            rhob -= Pb[p][q] * u[p] * u[q];
+            ub[p] -= 2.0f * rho * Pb[p][q] * u[q];
+        }
+    float jb[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        jb[p] = ub[p] * ir;
+        rhob -= ub[p] * u[p] * ir;
+        Fb[p] += fb[p] + (double)(0.5f * ub[p] * ir);
+    }
+    rdb += rhob;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int c[3] = {CX[i], CY[i], CZ[i]};
+        float m = (1.0f - om) * lam[i] + rdb + jb[0] * c[0] + jb[1] * c[1] + jb[2] * c[2];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (c[p] * c[q]) m += Pb[p][q] * c[p] * c[q];
+        mu[i] = m;
+    }
+}
+
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(kBlock) void k_adj_collide(AdjStepArgs ga)
+{
+    const StepArgs &a = ga.a;
+    const float *__restrict__ src = static_cast<const float *>(a.src);
+    const size_t Ns = (size_t)a.Ns;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int tid = threadIdx.x;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int r = t / a.ntx;
+    const int x = (t - r * a.ntx) * TX + tid % TX;
+    const int y = (r % a.nty) * TY + (tid / TX) % TY;
+    const int z = (r / a.nty) * TZ + tid / (TX * TY);
+    const bool in = x < nx && y < ny && z < nz;
+    const uint32_t idx = in ? (uint32_t)(x + nx * (y + ny * z)) : 0u;
+    const bool fluid = in && *at(a.own, idx) >= kVacated;
+    double Fb[3] = {0.0, 0.0, 0.0};
+    if (fluid) {
+        float g[kQ], lam[kQ], mu[kQ];
+        const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+        const int yp = y + 1 == ny ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+        const int zp = z + 1 == nz ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const int sx = CX[i] > 0 ? xm : (CX[i] < 0 ? xp : x);
+            const int sy = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
+            const int sz = CZ[i] > 0 ? zm : (CZ[i] < 0 ? zp : z);
+            g[i] = *at(src + (size_t)i * Ns, (uint32_t)(sx + nx * (sy + ny * sz)));
+            lam[i] = *at(ga.lam + (size_t)i * Ns, idx);
+        }
+        collide_adjoint(a, g, lam, mu, Fb);
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) *at(ga.mu + (size_t)i * Ns, idx) = mu[i];
+    } else if (in) {
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) *at(ga.mu + (size_t)i * Ns, idx) = 0.0f;
+    }
+    // body-force part: per-tile sums in a fixed order
+    __shared__ double s_red[kBlock / 64][3];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) Fb[p] += __shfl_xor(Fb[p], off);
+    if ((tid & 63) == 0)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) s_red[tid >> 6][p] = Fb[p];
+    __syncthreads();
+    if (tid < 3) {
+        double v = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) v += s_red[w][tid];
+        ga.dF_tile[3 * (size_t)t + tid] += v;
+    }
+}
+
+// Transpose of plain streaming: P_{n-1}(y)[i] went to f_n(y + c_i)[i] when
+// both nodes are fluid; boundary links add their parts afterwards.
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(kBlock) void k_adj_stream(StepArgs a, const float *mu, float *lam)
+{
+    const size_t Ns = (size_t)a.Ns;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int tid = threadIdx.x;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int r = t / a.ntx;
+    const int x = (t - r * a.ntx) * TX + tid % TX;
+    const int y = (r % a.nty) * TY + (tid / TX) % TY;
+    const int z = (r / a.nty) * TZ + tid / (TX * TY);
+    if (x >= nx || y >= ny || z >= nz) return;
+    const uint32_t idx = (uint32_t)(x + nx * (y + ny * z));
+    const bool fluid = *at(a.own, idx) >= kVacated;
+    const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+    const int yp = y + 1 == ny ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+    const int zp = z + 1 == nz ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int sx = CX[i] > 0 ? xp : (CX[i] < 0 ? xm : x);
+        const int sy = CY[i] > 0 ? yp : (CY[i] < 0 ? ym : y);
+        const int sz = CZ[i] > 0 ? zp : (CZ[i] < 0 ? zm : z);
+        const uint32_t d = (uint32_t)(sx + nx * (sy + ny * sz));   // y + c_i
+        float v = 0.0f;
+        if (fluid && *at(a.own, d) >= kVacated) v = *at(mu + (size_t)i * Ns, d);
+        *at(lam + (size_t)i * Ns, idx) = v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_reduce(const double *dF_tile, int n_tiles, double *dF)
+{
+    __shared__ double s_red[kBlock / 64][3];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < n_tiles; t += kBlock)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) v[p] += dF_tile[3 * (size_t)t + p];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) v[p] += __shfl_xor(v[p], off);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) s_red[threadIdx.x >> 6][p] = v[p];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += s_red[w][threadIdx.x];
+        dF[threadIdx.x] = s;
+    }
+}
+
 // The batched step kernel for a storage type and tile shape.
 template <int S>
 const void *batch_step_kernel_s(int shape)
@@ -335,6 +557,36 @@ hipError_t launch_batch_step(int storage, int shape, const BatchStepArgs &b, int
     BatchStepArgs arg = b;
     void *args[] = {&arg};
     return hipLaunchKernel(k, dim3(grid), dim3(kBlock), args, 0, s);
+}
+
+hipError_t launch_adj_collide(const AdjStepArgs &g, hipStream_t s)
+{
+    switch (g.a.tile) {
+    case kTile64x2x2: hipLaunchKernelGGL((k_adj_collide<64, 2, 2>), dim3(g.a.n_tiles), dim3(kBlock), 0, s, g); break;
+    case kTile32x4x2: hipLaunchKernelGGL((k_adj_collide<32, 4, 2>), dim3(g.a.n_tiles), dim3(kBlock), 0, s, g); break;
+    case kTile32x2x4: hipLaunchKernelGGL((k_adj_collide<32, 2, 4>), dim3(g.a.n_tiles), dim3(kBlock), 0, s, g); break;
+    case kTile16x8x2: hipLaunchKernelGGL((k_adj_collide<16, 8, 2>), dim3(g.a.n_tiles), dim3(kBlock), 0, s, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_stream(const StepArgs &a, const float *mu, float *lam, hipStream_t s)
+{
+    switch (a.tile) {
+    case kTile64x2x2: hipLaunchKernelGGL((k_adj_stream<64, 2, 2>), dim3(a.n_tiles), dim3(kBlock), 0, s, a, mu, lam); break;
+    case kTile32x4x2: hipLaunchKernelGGL((k_adj_stream<32, 4, 2>), dim3(a.n_tiles), dim3(kBlock), 0, s, a, mu, lam); break;
+    case kTile32x2x4: hipLaunchKernelGGL((k_adj_stream<32, 2, 4>), dim3(a.n_tiles), dim3(kBlock), 0, s, a, mu, lam); break;
+    case kTile16x8x2: hipLaunchKernelGGL((k_adj_stream<16, 8, 2>), dim3(a.n_tiles), dim3(kBlock), 0, s, a, mu, lam); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_reduce(const double *dF_tile, int n_tiles, double *dF, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(kBlock), 0, s, dF_tile, n_tiles, dF);
+    return hipGetLastError();
 }
 
 hipError_t launch_zieb_update(int storage, const ZiebArgs &z, hipStream_t s)

@@ -1,0 +1,111 @@
+"""The library's reverse-mode kernels (lbm_drag_gradient) against the FP64
+reference of oracle/adjoint.py.
+
+J = sum_b F_b,x after n steps from a fixed state, with fixed spheres; the
+gradient with respect to the body force and the sphere velocities.  The GPU
+runs FP32 forward and reverse steps, so the bar is relative to the size of
+each gradient: 1e-3 in norm (the FP32 parity bar of the step is 1e-5 on
+populations, and the gradient accumulates n steps of it).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import lbm_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(n=(24, 24, 24), n_spheres=3, seed=12):
+    case = W.case_box(n=n, n_spheres=n_spheres, radius=(3.0, 3.0), tau0=0.6, smag_c=0.1,
+                      body_force=(5e-6, 0.0, 0.0), u_sigma=0.0, gap=2.0, seed=seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 100))
+    return dataclasses.replace(case, V=rng.normal(0.0, 0.01, size=(n_spheres, 3)))
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("halfway", [False, True])
+def test_gradient_matches_fp64_reference(torch_stream, halfway):
+    import oracle
+    from oracle.adjoint import DragProblem
+    from paper_1703_05158_amd import Lattice
+    case = _case()
+    steps = 30
+    o = oracle.Oracle.from_case(case, halfway=halfway)
+    Jr, gFr, gVr = DragProblem(o).gradient(o.populations(), case.body_force, case.V, steps)
+    lat = Lattice.from_case(case, bb_mode="halfway" if halfway else "bouzidi", stream=torch_stream)
+    J, gF, gV = lat.drag_gradient(steps, 7)
+    print(f"J {J:.9e} ({Jr:.9e})  dF {gF} ({gFr})  dV err {_rel(gV, gVr):.2e}")
+    assert J == pytest.approx(Jr, rel=1e-5)
+    assert _rel(gF, gFr) < 1e-3
+    assert _rel(gV, gVr) < 1e-3
+    lat.close()
+
+
+def test_checkpoint_interval_and_final_state(torch_stream):
+    from paper_1703_05158_amd import Lattice
+    case = _case(n=(32, 24, 20), n_spheres=2, seed=5)
+    steps = 24
+    ref = Lattice.from_case(case, stream=torch_stream)
+    ref.step(steps)
+    P_ref = ref.get_populations()
+    F_ref = ref.get_forces()
+    out = []
+    for ckpt in (1, 5, 24, 100):
+        lat = Lattice.from_case(case, stream=torch_stream)
+        out.append(lat.drag_gradient(steps, ckpt))
+        assert np.array_equal(lat.get_populations(), P_ref)
+        F, T = lat.get_forces()
+        assert np.array_equal(F, F_ref[0]) and np.array_equal(T, F_ref[1])
+        assert lat.info()["steps_done"] == steps
+        lat.close()
+    J0, gF0, gV0 = out[0]
+    for J, gF, gV in out[1:]:
+        assert J == J0
+        assert _rel(gF, gF0) < 1e-5 and _rel(gV, gV0) < 1e-5
+    ref.close()
+
+
+def test_torch_function_and_directional_difference(torch_stream):
+    import torch
+    from paper_1703_05158_amd import Lattice, SphereDrag
+    case = _case()
+    lat = Lattice.from_case(case, stream=torch_stream)
+    start = lat.get_state()
+    fn = SphereDrag(lat, start, case.X, case.Omega, case.R, nsteps=20, ckpt=5)
+    F = torch.tensor(case.body_force, dtype=torch.float64, requires_grad=True)
+    V = torch.tensor(case.V, dtype=torch.float64, requires_grad=True)
+    J = fn(F, V)
+    gF, gV = torch.autograd.grad(J, (F, V))
+    J2, gF2, gV2 = Lattice.from_case(case, stream=torch_stream).drag_gradient(20, 5)
+    assert float(J) == pytest.approx(J2, rel=1e-12)
+    assert np.allclose(gF.numpy(), gF2, rtol=1e-5) and np.allclose(gV.numpy(), gV2, rtol=1e-5, atol=1e-9)
+    # J is linear in V: a directional difference on the GPU matches dJ/dV . d
+    rng = np.random.Generator(np.random.PCG64(4))
+    d = torch.tensor(rng.normal(size=case.V.shape))
+    h = 1e-3
+    with torch.no_grad():
+        Jp = float(fn(F, V + h * d))
+        Jm = float(fn(F, V - h * d))
+    fd = (Jp - Jm) / (2 * h)
+    assert fd == pytest.approx(float((gV * d).sum()), rel=1e-3)
+    lat.close()
+
+
+def test_drag_gradient_rejects_unsupported(torch_stream):
+    from paper_1703_05158_amd import LBMError, Lattice
+    case = _case(n=(16, 16, 16), n_spheres=1, seed=2)
+    lat = Lattice.from_case(case, storage="f16", stream=torch_stream)
+    with pytest.raises(LBMError):
+        lat.drag_gradient(4, 2)
+    lat.close()
+    duct = W.case_duct(nx=24, ny=24, nz=48, n_spheres=3, orifice_z=30, orifice_r_in=5, orifice_gap=2,
+                       pack_z=(4, 24), seed=3, drift=False)
+    lat = Lattice.from_case(duct, stream=torch_stream)
+    with pytest.raises(LBMError):
+        lat.drag_gradient(4, 2)   # walls
+    lat.close()
