@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--no-sweep", dest="sweep", action="store_false",
                     help="skip the batched 48-instance parameter sweep")
     ap.add_argument("--sweep-steps", type=int, default=500)
+    ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
+                    help="skip the drag-gradient run")
     ap.add_argument("--cpu-steps", type=int, default=15, help="oracle sample steps (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("OMP_NUM_THREADS", "16")))
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -135,9 +137,45 @@ def main():
         out["mixed_precision"] = mixed
     if args.sweep and args.storage == "f32" and not args.static:
         out["batched_sweep"] = sweep_run(args.sweep_steps)
+    if args.adjoint and args.storage == "f32" and not args.static:
+        out["adjoint"] = adjoint_run()
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps, args.cpu_threads)
     print(json.dumps(out), flush=True)
+
+
+def adjoint_run(steps=200, ckpt=20):
+    """Gradient of the summed sphere drag on the 96x96x192 box with 300
+    fixed spheres: the plain forward run of `steps` steps, then the gradient
+    (forward with a checkpoint every `ckpt` steps, reverse with recompute)
+    from the same start state."""
+    import numpy as np
+    import torch
+
+    import lbm_workloads as W
+    from paper_1703_05158_amd import Lattice
+
+    stream = torch.cuda.current_stream()
+    case = W.case_adjoint(steps=steps)
+    lat = Lattice.from_case(case, stream=stream.cuda_stream)
+    start = lat.get_state()
+    lat.step(5)
+    lat.set_state(start)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    lat.set_state(start)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, dF, dV = lat.drag_gradient(steps, ckpt)
+    t_grad = time.perf_counter() - t0
+    lat.close()
+    return {"workload": "periodic_96x96x192_300spheres", "steps": steps, "ckpt": ckpt,
+            "parameters": 3 + 3 * case.n_bodies, "J": J, "dJdF": [float(v) for v in dF],
+            "dJdV_norm": float(np.linalg.norm(dV)), "forward_ms": round(t_fwd * 1e3, 2),
+            "gradient_ms": round(t_grad * 1e3, 2), "gradient_over_forward": round(t_grad / t_fwd, 2)}
 
 
 def sweep_run(steps, warmup=20):

@@ -33,7 +33,7 @@ from typing import Optional
 import numpy as np
 
 __all__ = [
-    "Case", "rsa_pack", "min_tie_gap", "case_c0", "case_duct", "case_c1",
+    "Case", "rsa_pack", "min_tie_gap", "case_c0", "case_duct", "case_c1", "case_adjoint",
     "case_box", "drift_positions", "case_sweep_instances",
 ]
 
@@ -274,6 +274,21 @@ def case_sweep_instances(n_instances: int = 48, seed: int = 3, steps: int = 500)
                         tau0=tau0, smag_c=cs, body_force=(fmag, 0.0, 0.0), X=X,
                         V=np.zeros((nsph, 3)), Omega=np.zeros((nsph, 3)), R=R, steps=steps))
     return out
+
+
+def case_adjoint(seed: int = 4, steps: int = 200) -> Case:
+    """Drag-gradient workload: 96x96x192 periodic box, 300 spheres of radius
+    4 (RSA, 2-cell surface gap), body force 5e-6 along x, fluid at rest,
+    tau0 = 0.6, C = 0.1; sphere velocities N(0, 0.005^2) per component, held
+    in place (the gradient is taken with respect to the body force and the
+    300 x 3 velocities)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = 96, 96, 192
+    R = np.full(300, 4.0)
+    X = rsa_pack(rng, R, (0, 0, 0), (nx, ny, nz), gap=2.0, box=(nx, ny, nz))
+    V = rng.normal(0.0, 0.005, size=(300, 3))
+    return Case(name="adjoint_96x96x192_300spheres", nx=nx, ny=ny, nz=nz, tau0=0.6, smag_c=0.1,
+                body_force=(5e-6, 0.0, 0.0), X=X, V=V, Omega=np.zeros((300, 3)), R=R, steps=steps)
 
 
 def with_steps(case: Case, steps: int) -> Case:
