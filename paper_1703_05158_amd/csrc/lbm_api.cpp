@@ -58,6 +58,9 @@ struct lbm_ctx {
     int *flag_host = nullptr;
     double *scratch = nullptr;         // 4N doubles, export/import staging (lazy)
     double *pinned = nullptr;          // max_bodies * 10 doubles, set_bodies staging
+    int *order = nullptr;              // max_bodies: sphere order of the link pass (Morton order of the centres)
+    int *order_pin = nullptr;          // its host staging
+    int n_order = 0;                   // body count the order was made for (0: none)
     hipEvent_t stage_evt = nullptr;
     bool initialized = false;
     int steps_done = 0;
@@ -202,6 +205,7 @@ LinkArgs link_args(const lbm_ctx *h)
     la.n_walls = h->n_walls;
     la.n_wblk = h->n_walls > 0 ? h->n_wblk : 0;
     la.nb = h->nb_state;
+    la.order = h->n_order == h->nb_state ? h->order : nullptr;
     la.bodies = h->tab[h->ts];
     la.pop = h->pop[h->cur];
     return la;
@@ -446,10 +450,12 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         dalloc(h, &h->tab[1], sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->walls, sizeof(double) * kWallStride * std::max(c.max_walls, 1)) != hipSuccess ||
         dalloc(h, &h->acc, sizeof(double) * 6 * std::max(nbt, 1)) != hipSuccess ||
+        dalloc(h, &h->order, sizeof(int) * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->zstate, sizeof(ZiebState)) != hipSuccess ||
         dalloc(h, &h->flag, sizeof(int)) != hipSuccess)
         return bail(LBM_ERR_OOM);
     if (hipHostMalloc((void **)&h->pinned, sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
+        hipHostMalloc((void **)&h->order_pin, sizeof(int) * std::max(c.max_bodies, 1)) != hipSuccess ||
         hipHostMalloc((void **)&h->flag_host, sizeof(int)) != hipSuccess)
         return bail(LBM_ERR_OOM);
     if (hipEventCreateWithFlags(&h->stage_evt, hipEventDisableTiming) != hipSuccess) return bail(LBM_ERR_HIP);
@@ -475,10 +481,11 @@ void lbm_destroy(lbm_handle h)
     }
     free_wall_links(h);
     void *dev[] = {h->pop[0], h->pop[1], h->own, h->wall_map, h->tab[0], h->tab[1],
-                   h->walls, h->acc, h->flag, h->scratch, h->zstate};
+                   h->walls, h->acc, h->order, h->flag, h->scratch, h->zstate};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (h->pinned) (void)hipHostFree(h->pinned);
+    if (h->order_pin) (void)hipHostFree(h->order_pin);
     if (h->flag_host) (void)hipHostFree(h->flag_host);
     if (h->stage_evt) (void)hipEventDestroy(h->stage_evt);
     delete h;
@@ -521,10 +528,30 @@ lbm_status lbm_set_walls(lbm_handle h, const uint8_t *wall_id, int32_t n_walls, 
     return rasterize_full(h);
 }
 
+// Interleaved bits of the centre's cell (8 nodes a side) on each axis.
+static uint64_t morton_key(const double *X)
+{
+    uint64_t key = 0;
+    for (int a = 0; a < 3; ++a) {
+        const uint64_t c = (uint64_t)(X[a] / 8.0) & 0xFFFFF;
+        for (int bit = 0; bit < 20; ++bit) key |= ((c >> bit) & 1u) << (3 * bit + a);
+    }
+    return key;
+}
+
 static lbm_status stage_bodies(lbm_ctx *h, int32_t n)
 {
+    // the link pass takes the spheres in Morton order of their centres, so
+    // that the workgroups on one XCD work on neighbouring spheres, which
+    // share population lines; the order does not change any result
+    std::vector<std::pair<uint64_t, int>> keys((size_t)n);
+    for (int b = 0; b < n; ++b) keys[(size_t)b] = {morton_key(h->pinned + (size_t)b * kBodyStride), b};
+    std::sort(keys.begin(), keys.end());
+    for (int b = 0; b < n; ++b) h->order_pin[b] = keys[(size_t)b].second;
     HIP_TRY(h, hipMemcpyAsync(h->tab[1 - h->ts], h->pinned, sizeof(double) * kBodyStride * (size_t)n,
                               hipMemcpyHostToDevice, h->stream));
+    if (n > 0) HIP_TRY(h, hipMemcpyAsync(h->order, h->order_pin, sizeof(int) * (size_t)n, hipMemcpyHostToDevice, h->stream));
+    h->n_order = n;
     HIP_TRY(h, hipEventRecord(h->stage_evt, h->stream));
     h->nb_next = n;
     h->dirty = true;
@@ -626,6 +653,7 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
         la.n_walls = h->n_walls;
         la.n_wblk = h->n_walls > 0 ? h->n_wblk : 0;
         la.nb = h->nb_state;
+        la.order = h->n_order == h->nb_state ? h->order : nullptr;
         la.bodies = h->tab[h->ts];
         la.pop = h->pop[h->cur];
         if (h->zieb_z >= 0) HIP_TRY(h, launch_zieb_update(c.storage, zieb_args(h), h->stream));

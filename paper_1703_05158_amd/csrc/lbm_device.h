@@ -35,18 +35,22 @@ __host__ __device__ constexpr double wgt(int i)
     return i == 0 ? 1.0 / 3.0 : (((0x1C0Eu >> i) & 1u) ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
-// Storage of deviations g = f - w rho0.
+// Storage of deviations g = f - w rho0.  stnt is the store of the step
+// kernel's output: a non-temporal hint, since the whole next state streams
+// through the caches before any of it is read again.
 template <int S> struct Store;
 template <> struct Store<0> {
     using T = float;
     static __device__ __forceinline__ float ld(const T *p) { return *p; }
     static __device__ __forceinline__ void st(T *p, float v) { *p = v; }
+    static __device__ __forceinline__ void stnt(T *p, float v) { __builtin_nontemporal_store(v, p); }
     static __device__ __forceinline__ float round(float v) { return v; }
 };
 template <> struct Store<1> {
     using T = _Float16;
     static __device__ __forceinline__ float ld(const T *p) { return (float)*p; }
     static __device__ __forceinline__ void st(T *p, float v) { *p = (_Float16)v; }
+    static __device__ __forceinline__ void stnt(T *p, float v) { __builtin_nontemporal_store((_Float16)v, p); }
     static __device__ __forceinline__ float round(float v) { return (float)(_Float16)v; }
 };
 template <> struct Store<2> {  // bfloat16 as raw bits, round to nearest even
@@ -59,6 +63,7 @@ template <> struct Store<2> {  // bfloat16 as raw bits, round to nearest even
         return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
     }
     static __device__ __forceinline__ void st(T *p, float v) { *p = bits(v); }
+    static __device__ __forceinline__ void stnt(T *p, float v) { __builtin_nontemporal_store(bits(v), p); }
     static __device__ __forceinline__ float round(float v) { return __uint_as_float((uint32_t)bits(v) << 16); }
 };
 
@@ -79,6 +84,15 @@ __device__ __forceinline__ int wrap_add(int a, int d, int n)
 {
     const int r = a + d;
     return r < 0 ? r + n : (r >= n ? r - n : r);
+}
+
+// Workgroups go round-robin over the 8 XCDs: give each XCD a contiguous
+// range of the nblocks work items, so that neighbouring items share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int nblocks)
+{
+    const int per = nblocks >> 3;
+    if (b >= (per << 3)) return b;
+    return (b & 7) * per + (b >> 3);
 }
 
 // Wrap a coordinate known to lie in [-n, 2n).

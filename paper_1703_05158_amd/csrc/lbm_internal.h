@@ -82,6 +82,7 @@ struct LinkArgs {
     double *wl_part;              // [n_wblk][6]
     const int *wl_wblk;           // [n_walls + 1]: each wall's range of workgroups
     double *out;                  // [nb + n_walls][6]: F, T
+    const int *order;             // [nb]: the order in which spheres are taken (spatially sorted), or null
 };
 
 // One lattice of a batch: its step arguments for the batch's tile shape

@@ -162,9 +162,18 @@ __device__ __forceinline__ void link_finish(const LinkArgs &a, typename Store<S>
 constexpr int kItemCap = 4096;   // candidate links held at once
 constexpr int kRoundNodes = 224; // box nodes per round when a sphere has more (224 * 18 <= kItemCap)
 
+// Per-direction link counts packed two to a word: word w holds the opposite
+// directions w + 1 (bits 0-15) and w + 10 (bits 16-31); word kCW is the
+// total.
+constexpr int kCW = (kQ - 1) / 2;
+
+constexpr int kMaskCap = 4096;  // box nodes whose candidate masks are kept between the two passes
+
 struct SphereLds {
     uint32_t item[kItemCap];  // box node index << 5 | I
+    uint32_t mask[kMaskCap];  // candidate directions of each box node
     int wtot[kWaves];
+    uint32_t ctot[kWaves][kCW + 1];
 };
 
 // Candidate links of box node k: p is within a margin of the ball and more
@@ -219,6 +228,40 @@ __device__ __forceinline__ int block_scan(int cnt, int *wtot, int &tot)
         tot += t;
     }
     return pos;
+}
+
+// Exclusive prefix over the workgroup of each of the NW words (in v) and
+// their totals (in tot).
+template <int NW>
+__device__ __forceinline__ void block_scan_words(uint32_t (&v)[NW], uint32_t (*wtot)[NW], uint32_t (&tot)[NW])
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t incl[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) incl[w] = v[w];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t t = __shfl_up(incl[w], off);
+            if (lane >= off) incl[w] += t;
+        }
+    if (lane == 63)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) wtot[wv][w] = incl[w];
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        uint32_t pos = incl[w] - v[w], t = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) {
+            const uint32_t u = wtot[q][w];
+            if (q < wv) pos += u;
+            t += u;
+        }
+        v[w] = pos;
+        tot[w] = t;
+    }
 }
 
 // Links of the candidates listed in item[0, tot), two per thread at a time.
@@ -281,17 +324,43 @@ __device__ __forceinline__ void sphere_block(const LinkArgs &a, int b, SphereLds
         const float ri = (float)B[9] - 1.5f;
         const float in2 = ri > 0.0f ? ri * ri - mg : -1.0f;
         int px, py, pz, tot;
-        int cnt = 0;
-        for (int kk = tid; kk < total; kk += kBlock) cnt += __popc(candidates(a, bx, k, mg, in2, kk, px, py, pz));
-        int pos = block_scan(cnt, L.wtot, tot);
+        // Each thread takes a contiguous run of box nodes.  The list is
+        // ordered by direction, then by box node, so that the lanes of one
+        // load instruction read neighbouring nodes of one population array;
+        // each direction I is followed by its opposite, since the links of
+        // both read the arrays I and opposite(I).
+        const int per = (total + kBlock - 1) / kBlock;
+        const int k0 = tid * per, k1 = min(total, k0 + per);
+        uint32_t cw[kCW + 1];
+#pragma unroll
+        for (int w = 0; w <= kCW; ++w) cw[w] = 0;
+        const bool keep = total <= kMaskCap;
+        for (int kk = k0; kk < k1; ++kk) {
+            const uint32_t lm = candidates(a, bx, k, mg, in2, kk, px, py, pz);
+            if (keep) L.mask[kk] = lm;
+#pragma unroll
+            for (int w = 0; w < kCW; ++w) cw[w] += ((lm >> (w + 1)) & 1u) | (((lm >> (w + 10)) & 1u) << 16);
+            cw[kCW] += __popc(lm);
+        }
+        uint32_t ct[kCW + 1];
+        block_scan_words<kCW + 1>(cw, L.ctot, ct);
+        tot = (int)ct[kCW];
         if (tot <= kItemCap) {
-            for (int kk = tid; kk < total; kk += kBlock) {
-                uint32_t lm = candidates(a, bx, k, mg, in2, kk, px, py, pz);
-                while (lm) {
-                    const int I = __builtin_ctz(lm);
-                    lm &= lm - 1;
-                    L.item[pos++] = ((uint32_t)kk << 5) | (uint32_t)I;
-                }
+            // no field exceeds kItemCap, so none carried into its neighbour
+            uint32_t pos[kQ - 1];
+            uint32_t base = 0;
+#pragma unroll
+            for (int w = 0; w < kCW; ++w) {
+                pos[w] = base + (cw[w] & 0xFFFFu);
+                base += ct[w] & 0xFFFFu;
+                pos[w + 9] = base + (cw[w] >> 16);
+                base += ct[w] >> 16;
+            }
+            for (int kk = k0; kk < k1; ++kk) {
+                const uint32_t lm = keep ? L.mask[kk] : candidates(a, bx, k, mg, in2, kk, px, py, pz);
+#pragma unroll
+                for (int I = 1; I < kQ; ++I)
+                    if ((lm >> I) & 1u) L.item[pos[I - 1]++] = ((uint32_t)kk << 5) | (uint32_t)I;
             }
             __syncthreads();
             process_items<S>(a, pop, bx, k, own_b, L.item, tot, acc);
@@ -301,7 +370,7 @@ __device__ __forceinline__ void sphere_block(const LinkArgs &a, int b, SphereLds
                 const int kk = base + tid;
                 uint32_t lm = 0;
                 if (tid < kRoundNodes && kk < total) lm = candidates(a, bx, k, mg, in2, kk, px, py, pz);
-                pos = block_scan(__popc(lm), L.wtot, tot);
+                int pos = block_scan(__popc(lm), L.wtot, tot);
                 while (lm) {
                     const int I = __builtin_ctz(lm);
                     lm &= lm - 1;
@@ -390,11 +459,12 @@ __global__ __launch_bounds__(kBlock) void k_links(LinkArgs a)
     __shared__ double s_red[kWaves][6];
     const int b = blockIdx.x;
     if (b < a.nb) {
-        // workgroups go round-robin over the 8 XCDs: give each XCD a
-        // contiguous range of spheres, so that spheres that are neighbours
-        // in the table share an L2
-        const int per = a.nb >> 3;
-        sphere_block<S>(a, b >= (per << 3) ? b : (b & 7) * per + (b >> 3), L, s_red);
+        // workgroups go round-robin over the 8 XCDs: each XCD takes a
+        // contiguous range of the spheres in processing order (Morton order
+        // of the centres when the host set them), so that neighbouring
+        // spheres, which share population lines, share an L2
+        const int sb = xcd_remap(b, a.nb);
+        sphere_block<S>(a, a.order ? a.order[sb] : sb, L, s_red);
     }
     else
         wall_block<S>(a, b - a.nb, s_red);

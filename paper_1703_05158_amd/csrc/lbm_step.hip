@@ -25,16 +25,6 @@ namespace {
 
 using namespace dev;
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of tiles so that the y/z neighbour rows a tile pulls were
-// brought into the same XCD's L2 by the tiles just before it.
-__device__ __forceinline__ int xcd_remap(int b, int nblocks)
-{
-    const int per = nblocks >> 3;
-    if (b >= (per << 3)) return b;
-    return (b & 7) * per + (b >> 3);
-}
-
 // Inflow plane of a virtual cylinder (Sec. 2.6), on the streamed deviations
 // g of a plane node: the directions from the removed domain (c_z = +1) were
 // not received and keep the node's own values; with rho* the node's density,
@@ -169,7 +159,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int t)
         {   // rest population: equilibrium deviation w0 (rd - 1.5 rho uu), source -3 w0 cf uF
             const float w = (float)wgt(0);
             const float v = om1 * g[0] + om * w * (rd - 1.5f * rho * uu) - 3.0f * w * cf * uF;
-            St::st(at(dst, idx), fluid ? v : 0.0f);
+            St::stnt(at(dst, idx), fluid ? v : 0.0f);
         }
 #pragma unroll
         for (int i = 1; i <= 9; ++i) {
@@ -181,8 +171,8 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int t)
             const float ev = om * w * (rd + rho * (4.5f * cu * cu - 1.5f * uu)) + w * cf * (9.0f * cu * cF - 3.0f * uF);
             const float od = 3.0f * w * (om * rho * cu + cf * cF);
             const float vp = om1 * g[i] + ev + od, vm = om1 * g[i + 9] + ev - od;
-            St::st(at(dst + (size_t)i * Ns, idx), fluid ? vp : 0.0f);
-            St::st(at(dst + (size_t)(i + 9) * Ns, idx), fluid ? vm : 0.0f);
+            St::stnt(at(dst + (size_t)i * Ns, idx), fluid ? vp : 0.0f);
+            St::stnt(at(dst + (size_t)(i + 9) * Ns, idx), fluid ? vm : 0.0f);
         }
     }
 }
