@@ -95,6 +95,22 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks)
     return (b & 7) * per + (b >> 3);
 }
 
+// A copy of v that the compiler knows to be the same in every lane (the
+// value of the first active lane), so that it can live in scalar registers:
+// for argument blocks that a persistent kernel loads from memory.
+template <typename T>
+__device__ __forceinline__ T uniform(const T &v)
+{
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    int w[sizeof(T) / 4];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    T r;
+    __builtin_memcpy(&r, w, sizeof(T));
+    return r;
+}
+
 // Wrap a coordinate known to lie in [-n, 2n).
 __device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 

@@ -7,8 +7,9 @@
 // settle every old sphere's box: a node still tagged kVacated | id was
 // uncovered and is refilled with the equilibrium at rho0 and the velocity it
 // had as a solid (the solid-side Maxwell equilibrium of Sec. 2.3).  One
-// workgroup per sphere walks the sphere's bounding box with an 8x8x4 thread
-// block.
+// workgroup per sphere walks the sphere's bounding box: vacate and settle
+// with an 8x8x4 thread block, stamp in chunks whose owner codes each thread
+// loads together.
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -35,6 +36,54 @@ __device__ __forceinline__ void for_box(const Box &bx, int nx, int ny, int nz, F
                 f(px, py, pz, px + nx * (py + ny * pz));
             }
         }
+    }
+}
+
+constexpr int kBoxU = 8;  // box nodes per thread whose owner loads are in flight together
+
+// Node k (x fastest) of a body's box: its coordinates and index.
+struct BoxNode {
+    int px, py, pz;
+    uint32_t n;
+};
+
+__device__ __forceinline__ BoxNode box_node(const Box &bx, int k, int nx, int ny, int nz)
+{
+    const int kx = k % bx.ex, r = k / bx.ex;
+    BoxNode v;
+    v.px = wrap1(bx.x0 + kx, nx);
+    v.py = wrap1(bx.y0 + r % bx.ey, ny);
+    v.pz = wrap1(bx.z0 + r / bx.ey, nz);
+    v.n = (uint32_t)(v.px + nx * (v.py + ny * v.pz));
+    return v;
+}
+
+// The nodes of a body's box in chunks of kBoxU per thread (a 1-D
+// workgroup): the owner codes of a chunk are loaded together (keep(node)
+// selects the nodes to load), then act(node, owner) runs on each loaded node.
+template <typename Keep, typename Act>
+__device__ __forceinline__ void box_chunks(const Box &bx, int nx, int ny, int nz, const uint16_t *own, Keep &&keep,
+                                           Act &&act)
+{
+    const int total = bx.ex * bx.ey * bx.ez;
+    for (int base = 0; base < total; base += kBoxU * kBlock) {
+        BoxNode v[kBoxU];
+        uint16_t o[kBoxU];
+        bool ld[kBoxU];
+#pragma unroll
+        for (int u = 0; u < kBoxU; ++u) {
+            const int k = base + u * kBlock + (int)threadIdx.x;
+            ld[u] = false;
+            o[u] = 0;
+            if (k < total) {
+                v[u] = box_node(bx, k, nx, ny, nz);
+                ld[u] = keep(v[u]);
+                if (ld[u]) o[u] = own[v[u].n];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kBoxU; ++u)
+            if (ld[u]) act(v[u], o[u]);
     }
 }
 
@@ -82,9 +131,14 @@ __global__ __launch_bounds__(kBlock) void k_stamp(GeomArgs g)
     const uint16_t id = (uint16_t)(g.n_walls + blockIdx.x);
     uint16_t *own = g.own;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
-    for_box(body_box(B, 0), nx, ny, nz, [&](int px, int py, int pz, int n) {
-        if (inside(B, px, py, pz, nx, ny, nz)) atomic_min_u16(own + n, id);
-    });
+    // a plain read first: owners only decrease while spheres are stamped, so
+    // a node that reads id or lower needs no atomic (the common case when a
+    // sphere has moved by less than a node)
+    box_chunks(
+        body_box(B, 0), nx, ny, nz, own, [&](const BoxNode &v) { return inside(B, v.px, v.py, v.pz, nx, ny, nz); },
+        [&](const BoxNode &v, uint16_t o) {
+            if (o > id) atomic_min_u16(own + v.n, id);
+        });
 }
 
 // Refill the nodes the old sphere `blockIdx.x` uncovered: the equilibrium at
@@ -266,7 +320,7 @@ hipError_t launch_vacate(const GeomArgs &g, hipStream_t s)
 hipError_t launch_stamp(const GeomArgs &g, hipStream_t s)
 {
     if (g.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_stamp, dim3(g.nb), kBoxBlock, 0, s, g);
+    hipLaunchKernelGGL(k_stamp, dim3(g.nb), dim3(kBlock), 0, s, g);
     return hipGetLastError();
 }
 

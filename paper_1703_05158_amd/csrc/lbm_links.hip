@@ -624,8 +624,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_links(BatchLinkArgs b)
             const BatchMember &bm = b.members[m];
             mb = bm.item_begin;
             me = m + 1 < b.n ? b.members[m + 1].item_begin : b.total_items;
-            a = bm.links;
-            a.pop = bm.pop[b.cur[m]];
+            LinkArgs t = bm.links;
+            t.pop = bm.pop[b.cur[m]];
+            a = uniform(t);
         }
         const int j = g - mb;
         if (j < a.nb)

@@ -207,10 +207,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(BatchStepArgs b)
             const BatchMember &bm = b.members[m];
             mb = bm.tile_begin;
             me = m + 1 < b.n ? b.members[m + 1].tile_begin : b.total_tiles;
-            a = bm.step;
+            StepArgs t = bm.step;
             const int c = b.cur[m];
-            a.src = bm.pop[c];
-            a.dst = bm.pop[c ^ 1];
+            t.src = bm.pop[c];
+            t.dst = bm.pop[c ^ 1];
+            a = uniform(t);
         }
         tile_step<S, TX, TY, TZ>(a, g - mb);
     }
