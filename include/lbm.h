@@ -133,8 +133,10 @@ lbm_status lbm_set_walls(lbm_handle h, const uint8_t *wall_id, int32_t n_walls,
  * The bodies given before step k are the geometry and velocities of step k;
  * nodes that turn from solid to fluid are refilled with the equilibrium at
  * rho0 and the velocity they had as solids.  The copy is asynchronous on the
- * handle's stream (pinned staging).  Errors: ARG (null with n > 0, ranges,
- * non-finite values), CAPACITY (n > max_bodies). */
+ * handle's stream (pinned staging).  The link pass takes the spheres in
+ * Morton order of the centres given here (kept for later device tables of
+ * the same count); no result depends on that order.  Errors: ARG (null with
+ * n > 0, ranges, non-finite values), CAPACITY (n > max_bodies). */
 lbm_status lbm_set_bodies(lbm_handle h, int32_t n, const double *X, const double *V,
                           const double *Omega, const double *R);
 

@@ -181,16 +181,8 @@ struct SphereLds {
 // (p, I) when p + c_I lies outside the ball by the same margin.  The margin
 // covers the FP32 rounding, so every link is a candidate; the owner map then
 // decides exactly.
-__device__ __forceinline__ uint32_t candidates(const LinkArgs &a, const Box &bx, const SphereK &k, float mg,
-                                               float in2, int kk, int &px, int &py, int &pz)
+__device__ __forceinline__ uint32_t cand_mask(const SphereK &k, float mg, float in2, float dx, float dy, float dz)
 {
-    const int kx = kk % bx.ex, kr = kk / bx.ex;
-    px = wrap1(bx.x0 + kx, a.nx);
-    py = wrap1(bx.y0 + kr % bx.ey, a.ny);
-    pz = wrap1(bx.z0 + kr / bx.ey, a.nz);
-    const float dx = (float)min_image((double)px - k.X0, a.nx);
-    const float dy = (float)min_image((double)py - k.X1, a.ny);
-    const float dz = (float)min_image((double)pz - k.X2, a.nz);
     const float d2 = dx * dx + dy * dy + dz * dz;
     uint32_t lm = 0;
     if (d2 <= k.R2 + mg && d2 >= in2) {
@@ -206,6 +198,28 @@ __device__ __forceinline__ uint32_t candidates(const LinkArgs &a, const Box &bx,
     }
     return lm;
 }
+
+// The same for box node kk (x fastest), with its coordinates.
+__device__ __forceinline__ uint32_t candidates(const LinkArgs &a, const Box &bx, const SphereK &k, float mg,
+                                               float in2, int kk, int &px, int &py, int &pz)
+{
+    const int kx = kk % bx.ex, kr = kk / bx.ex;
+    px = wrap1(bx.x0 + kx, a.nx);
+    py = wrap1(bx.y0 + kr % bx.ey, a.ny);
+    pz = wrap1(bx.z0 + kr / bx.ey, a.nz);
+    const float dx = (float)min_image((double)px - k.X0, a.nx);
+    const float dy = (float)min_image((double)py - k.X1, a.ny);
+    const float dz = (float)min_image((double)pz - k.X2, a.nz);
+    return cand_mask(k, mg, in2, dx, dy, dz);
+}
+
+// Offset of box coordinate v (unwrapped) from the centre coordinate c.  A
+// box spans at most 2R + 1 < n - 1 nodes around the centre, so this is the
+// minimum image.
+__device__ __forceinline__ float box_off(int v, double c) { return (float)((double)v - c); }
+
+// Number of bits that hold 0 .. e - 1.
+__device__ __forceinline__ int field_bits(int e) { return e > 1 ? 32 - __clz(e - 1) : 1; }
 
 // Exclusive prefix of `cnt` over the workgroup and the total.
 __device__ __forceinline__ int block_scan(int cnt, int *wtot, int &tot)
@@ -264,30 +278,45 @@ __device__ __forceinline__ void block_scan_words(uint32_t (&v)[NW], uint32_t (*w
     }
 }
 
+// Box node of a list item (node << 5 | I): packed coordinates kx | ky << wx
+// | kz << (wx + wy) when wx > 0, else the box index.
+__device__ __forceinline__ void item_node(const LinkArgs &a, const Box &bx, int wx, int wy, uint32_t it, int &px,
+                                          int &py, int &pz)
+{
+    const uint32_t v = it >> 5;
+    int kx, ky, kz;
+    if (wx > 0) {
+        kx = (int)(v & ((1u << wx) - 1u));
+        ky = (int)((v >> wx) & ((1u << wy) - 1u));
+        kz = (int)(v >> (wx + wy));
+    } else {
+        kx = (int)v % bx.ex;
+        ky = ((int)v / bx.ex) % bx.ey;
+        kz = (int)v / (bx.ex * bx.ey);
+    }
+    px = wrap1(bx.x0 + kx, a.nx);
+    py = wrap1(bx.y0 + ky, a.ny);
+    pz = wrap1(bx.z0 + kz, a.nz);
+}
+
 // Links of the candidates listed in item[0, tot), two per thread at a time.
 template <int S>
 __device__ __forceinline__ void process_items(const LinkArgs &a, typename Store<S>::T *pop, const Box &bx,
                                               const SphereK &k, uint16_t own_b, const uint32_t *item, int tot,
-                                              double (&acc)[6])
+                                              int wx, int wy, double (&acc)[6])
 {
 #pragma unroll 1
     for (int j = threadIdx.x; j < tot; j += 2 * kBlock) {
         const int j2 = j + kBlock;
         int px, py, pz;
         const uint32_t ia = item[j];
-        const int ka = (int)(ia >> 5);
-        px = wrap1(bx.x0 + ka % bx.ex, a.nx);
-        py = wrap1(bx.y0 + (ka / bx.ex) % bx.ey, a.ny);
-        pz = wrap1(bx.z0 + ka / (bx.ex * bx.ey), a.nz);
+        item_node(a, bx, wx, wy, ia, px, py, pz);
         const LinkLoad la = link_load<S>(a, pop, k, px, py, pz, (int)(ia & 31));
         LinkLoad lb;
         lb.op = 0;  // no second link: fails the ownership test
         if (j2 < tot) {
             const uint32_t ib = item[j2];
-            const int kb = (int)(ib >> 5);
-            px = wrap1(bx.x0 + kb % bx.ex, a.nx);
-            py = wrap1(bx.y0 + (kb / bx.ex) % bx.ey, a.ny);
-            pz = wrap1(bx.z0 + kb / (bx.ex * bx.ey), a.nz);
+            item_node(a, bx, wx, wy, ib, px, py, pz);
             lb = link_load<S>(a, pop, k, px, py, pz, (int)(ib & 31));
         }
         link_finish<S>(a, pop, own_b, la, acc);
@@ -335,8 +364,19 @@ __device__ __forceinline__ void sphere_block(const LinkArgs &a, int b, SphereLds
 #pragma unroll
         for (int w = 0; w <= kCW; ++w) cw[w] = 0;
         const bool keep = total <= kMaskCap;
+        // box coordinates of node k0, then stepped along the run
+        int kx = k0 % bx.ex, ky = (k0 / bx.ex) % bx.ey, kz = k0 / (bx.ex * bx.ey);
+        float dy = box_off(bx.y0 + ky, k.X1), dz = box_off(bx.z0 + kz, k.X2);
         for (int kk = k0; kk < k1; ++kk) {
-            const uint32_t lm = candidates(a, bx, k, mg, in2, kk, px, py, pz);
+            const uint32_t lm = cand_mask(k, mg, in2, box_off(bx.x0 + kx, k.X0), dy, dz);
+            if (++kx == bx.ex) {
+                kx = 0;
+                if (++ky == bx.ey) {
+                    ky = 0;
+                    dz = box_off(bx.z0 + ++kz, k.X2);
+                }
+                dy = box_off(bx.y0 + ky, k.X1);
+            }
             if (keep) L.mask[kk] = lm;
 #pragma unroll
             for (int w = 0; w < kCW; ++w) cw[w] += ((lm >> (w + 1)) & 1u) | (((lm >> (w + 10)) & 1u) << 16);
@@ -356,14 +396,32 @@ __device__ __forceinline__ void sphere_block(const LinkArgs &a, int b, SphereLds
                 pos[w + 9] = base + (cw[w] >> 16);
                 base += ct[w] >> 16;
             }
+            // list items carry the packed box coordinates when they fit
+            const int wx = field_bits(bx.ex), wy = field_bits(bx.ey);
+            const bool packed = wx + wy + field_bits(bx.ez) <= 27;
+            kx = k0 % bx.ex;
+            ky = (k0 / bx.ex) % bx.ey;
+            kz = k0 / (bx.ex * bx.ey);
+            dy = box_off(bx.y0 + ky, k.X1);
+            dz = box_off(bx.z0 + kz, k.X2);
             for (int kk = k0; kk < k1; ++kk) {
-                const uint32_t lm = keep ? L.mask[kk] : candidates(a, bx, k, mg, in2, kk, px, py, pz);
+                const uint32_t lm = keep ? L.mask[kk] : cand_mask(k, mg, in2, box_off(bx.x0 + kx, k.X0), dy, dz);
+                const uint32_t node =
+                    packed ? (uint32_t)kx | ((uint32_t)ky << wx) | ((uint32_t)kz << (wx + wy)) : (uint32_t)kk;
 #pragma unroll
                 for (int I = 1; I < kQ; ++I)
-                    if ((lm >> I) & 1u) L.item[pos[I - 1]++] = ((uint32_t)kk << 5) | (uint32_t)I;
+                    if ((lm >> I) & 1u) L.item[pos[I - 1]++] = (node << 5) | (uint32_t)I;
+                if (++kx == bx.ex) {
+                    kx = 0;
+                    if (++ky == bx.ey) {
+                        ky = 0;
+                        dz = box_off(bx.z0 + ++kz, k.X2);
+                    }
+                    dy = box_off(bx.y0 + ky, k.X1);
+                }
             }
             __syncthreads();
-            process_items<S>(a, pop, bx, k, own_b, L.item, tot, acc);
+            process_items<S>(a, pop, bx, k, own_b, L.item, tot, packed ? wx : 0, wy, acc);
         } else {
             for (int base = 0; base < total; base += kRoundNodes) {
                 __syncthreads();  // item and wtot of the previous pass are free
@@ -377,7 +435,7 @@ __device__ __forceinline__ void sphere_block(const LinkArgs &a, int b, SphereLds
                     L.item[pos++] = ((uint32_t)kk << 5) | (uint32_t)I;
                 }
                 __syncthreads();
-                process_items<S>(a, pop, bx, k, own_b, L.item, tot, acc);
+                process_items<S>(a, pop, bx, k, own_b, L.item, tot, 0, 0, acc);
             }
         }
     }

@@ -111,6 +111,46 @@ def test_device_body_table_matches_host(torch_stream):
     b.close()
 
 
+def test_sphere_order_changes_no_result(torch_stream):
+    """The link pass takes the spheres in Morton order of the centres set from
+    the host: the same spheres listed in another order give the same state
+    and, sphere by sphere, the same forces, bit for bit (drift, host and
+    device tables)."""
+    import dataclasses
+
+    import torch
+    from paper_1703_05158_amd import Lattice
+    case = W.case_box(n=(40, 36, 44), n_spheres=12, radius=(2.0, 5.0), v_sigma=0.02, w_sigma=0.01,
+                      seed=8, drift=True)
+    perm = np.random.Generator(np.random.PCG64(3)).permutation(case.n_bodies)
+    case_p = dataclasses.replace(case, X=case.X[perm], V=case.V[perm], Omega=case.Omega[perm], R=case.R[perm])
+    a = Lattice.from_case(case, stream=torch_stream)
+    b = Lattice.from_case(case_p, stream=torch_stream)
+    nw = a.info()["n_walls"]
+    for n in range(1, 9):
+        X, V, Om, R = case.bodies_at(n)
+        if n % 2:
+            a.set_bodies(X, V, Om, R)
+            b.set_bodies(X[perm], V[perm], Om[perm], R[perm])
+        else:
+            tab = np.concatenate([X, V, Om, R[:, None]], 1)
+            a.set_bodies_device(len(R), torch.tensor(tab, device="cuda"))
+            b.set_bodies_device(len(R), torch.tensor(tab[perm], device="cuda"))
+        a.step(1)
+        b.step(1)
+    np.testing.assert_array_equal(a.get_populations(), b.get_populations())
+    own_a, own_b = a.get_owner(), b.get_owner()
+    inv = np.argsort(perm)
+    mapped = np.where(own_a >= nw, inv[np.clip(own_a - nw, 0, None)] + nw, own_a)
+    np.testing.assert_array_equal(own_b, mapped)
+    Fa, Ta = a.get_forces()
+    Fb, Tb = b.get_forces()
+    np.testing.assert_array_equal(Fb, Fa[perm])
+    np.testing.assert_array_equal(Tb, Ta[perm])
+    a.close()
+    b.close()
+
+
 def test_owner_map_matches_oracle(torch_stream):
     case = W.case_duct(nx=40, ny=36, nz=96, n_spheres=60, orifice_z=70, orifice_r_in=10,
                        orifice_gap=3, pack_z=(6, 64), v_sigma=0.05, seed=5)
