@@ -50,7 +50,20 @@ def measured_traffic(storage):
     return rec.get("bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(case, sample_steps, threads):
+    """The FP64 oracle on the host's cores over a bounded sample of the same
+    workload, then one step of it on a single thread."""
     import oracle
     used = oracle.set_threads(threads)
     o = oracle.Oracle.from_case(case)
@@ -59,10 +72,39 @@ def cpu_baseline(case, sample_steps, threads):
         o.set_bodies(*case.bodies_at(n))
         o.step(1)
     dt = time.perf_counter() - t0
+    oracle.set_threads(1)
+    o.set_bodies(*case.bodies_at(sample_steps + 1))
+    t1 = time.perf_counter()
+    o.step(1)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
     return {"value": round(case.n_nodes * sample_steps / dt / 1e6, 3), "unit": "MLUPS",
             "cores": used, "kind": "oracle",
             "sample": f"{sample_steps} drift steps of the same 128x128x512 duct (FP64 C oracle, "
-                      f"OpenMP over z), {dt:.1f} s"}
+                      f"OpenMP over z), {dt:.1f} s",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "single_thread": {"value": round(case.n_nodes / dt1 / 1e6, 3), "unit": "MLUPS",
+                              "sample": f"1 drift step on 1 thread, {dt1:.1f} s"}}
+
+
+def copy_bandwidth():
+    """Device-to-device copy of 1 GiB (read + write), GB/s: the practical
+    bandwidth reference beside the HBM peak."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return 2 * (1 << 30) / sec / 1e9
 
 
 def main():
@@ -108,6 +150,9 @@ def main():
     case = W.case_c1(drift=not args.static)
     K, Wm = args.steps, args.warmup
     main_run = timed_run(case, args.storage, K, Wm)
+    copy_gbs = copy_bandwidth()
+    main_run["roofline"]["copy_gbs"] = round(copy_gbs, 1)
+    main_run["roofline"]["frac_of_copy"] = round(main_run["roofline"]["achieved"] / copy_gbs, 4)
     N = case.n_nodes
     out = {
         "metric": METRIC, "value": main_run["value"], "unit": "MLUPS", "n_gpus": 1,
@@ -119,6 +164,7 @@ def main():
                    "per_step": "set_bodies_device + step + get_forces_device" if case.drift
                    else "step + get_forces_device"},
         "mflups": main_run["mflups"],
+        "ms_per_step_host_forces": main_run["ms_per_step_host_forces"],
         "roofline": main_run["roofline"],
     }
     if args.mixed and args.storage == "f32" and not args.static:
@@ -141,6 +187,7 @@ def main():
         out["adjoint"] = adjoint_run()
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps, args.cpu_threads)
+        out["cpu_baseline"]["gpu_over_oracle"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
     print(json.dumps(out), flush=True)
 
 
@@ -240,9 +287,10 @@ def timed_run(case, storage, K, Wm):
     nbt = nb + case.n_walls
     # per-step kinematics, resident in HBM before timing (the DEM's output)
     tabs = None
+    K2 = min(K, 50)
     if case.drift:
-        tabs = torch.empty((Wm + K, nb, 10), dtype=torch.float64, device="cuda")
-        for n in range(1, Wm + K + 1):
+        tabs = torch.empty((Wm + K + K2, nb, 10), dtype=torch.float64, device="cuda")
+        for n in range(1, Wm + K + K2 + 1):
             X, V, Om, R = case.bodies_at(n)
             tabs[n - 1] = torch.from_numpy(np.concatenate([X, V, Om, R[:, None]], 1))
     hist = torch.zeros((K, nbt, 6), dtype=torch.float64, device="cuda")
@@ -269,6 +317,15 @@ def timed_run(case, storage, K, Wm):
     lat.profile(False)
     n_fluid_end = lat.count_fluid()
     assert torch.isfinite(hist).all().item()
+    # K2 more steps with the forces copied to the host after every step
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(K2):
+        if tabs is not None:
+            lat.set_bodies_device(nb, tabs[Wm + K + n])
+        lat.step(1)
+        lat.get_forces()
+    dt_host = time.perf_counter() - t0
     lat.close()
 
     N = case.n_nodes
@@ -286,6 +343,7 @@ def timed_run(case, storage, K, Wm):
             "kernel": f"k_step<{storage}>", "kernel_ms": round(k_avg_s * 1e3, 4),
             "alg_bytes_per_launch": int(alg_bytes)}
     return {"value": round(N * K / dt / 1e6, 1), "ms_per_step": round(dt / K * 1e3, 4),
+            "ms_per_step_host_forces": round(dt_host / K2 * 1e3, 4),
             "mflups": round(nf * K / dt / 1e6, 1), "fluid_nodes": int(nf), "roofline": roof}
 
 
@@ -321,9 +379,13 @@ def precision_errors(case):
                 umax = float(np.max(np.linalg.norm(ur, axis=0)))
                 F, _ = lat.get_forces()
                 Fr = ref[f"F_{n}"]
+                dr = rho.ravel()[idx] - ref[f"rho_{n}"]
+                du = np.linalg.norm(u.reshape(3, -1)[:, idx] - ur, axis=0)
                 e[f"step_{n}"] = {
-                    "rho_abs": float(np.max(np.abs(rho.ravel()[idx] - ref[f"rho_{n}"]))),
-                    "u_abs": float(np.max(np.linalg.norm(u.reshape(3, -1)[:, idx] - ur, axis=0))),
+                    "rho_abs": float(np.max(np.abs(dr))),
+                    "rho_rms": float(np.sqrt(np.mean(dr * dr))),
+                    "u_abs": float(np.max(du)),
+                    "u_rms": float(np.sqrt(np.mean(du * du))),
                     "u_max": umax,
                     "force_rel": float(np.max(np.linalg.norm(F - Fr, axis=1)) / np.max(np.linalg.norm(Fr, axis=1))),
                     "sampled_nodes": int(len(idx))}
