@@ -658,7 +658,12 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
         la.pop = h->pop[h->cur];
         if (h->zieb_z >= 0) HIP_TRY(h, launch_zieb_update(c.storage, zieb_args(h), h->stream));
         HIP_TRY(h, launch_links(c.storage, la, h->stream));
-        HIP_TRY(h, launch_wall_forces(la, h->stream));
+        // the step kernel's first workgroups add up the wall chunks
+        a.n_wsum = la.n_walls;
+        a.wsum_nb = la.nb;
+        a.wsum_part = h->wl_part;
+        a.wsum_wblk = h->wl_wblk;
+        a.wsum_out = h->acc;
         a.src = h->pop[h->cur];
         a.dst = h->pop[1 - h->cur];
         hipEvent_t e0 = nullptr, e1 = nullptr;

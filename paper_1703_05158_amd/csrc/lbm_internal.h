@@ -44,6 +44,12 @@ struct StepArgs {
     int *flag;                    // NaN guard, may be null
     int zieb_z;                   // z of the inflow plane fed by a virtual cylinder, -1 = none
     const double *zieb_state;     // ZiebState: rho is the cylinder density of this step
+    // wall totals of the link pass that preceded this step: workgroup w <
+    // n_wsum adds the chunk sums of wall w into wsum_out[6 (wsum_nb + w)]
+    int n_wsum, wsum_nb;
+    const double *wsum_part;      // [chunks][6]
+    const int *wsum_wblk;         // [n_walls + 1]: each wall's range of chunks
+    double *wsum_out;
 };
 
 // Zoom-in with Effective Boundaries (Sec. 2.6): the state of the virtual
@@ -145,7 +151,6 @@ struct GeomArgs {
 // storage: 0 = fp32, 1 = fp16, 2 = bf16 deviations
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t s);
 hipError_t launch_links(int storage, const LinkArgs &a, hipStream_t s);
-hipError_t launch_wall_forces(const LinkArgs &a, hipStream_t s);
 hipError_t launch_batch_step(int storage, int shape, const BatchStepArgs &b, int grid, hipStream_t s);
 int batch_step_blocks_per_cu(int storage, int shape);   // resident workgroups per CU of the persistent kernels
 int batch_links_blocks_per_cu(int storage);

@@ -16,7 +16,7 @@
 //    per thread in flight) and reduces force and torque itself;
 //  - wall links do not change while the walls stay: their fluid nodes are
 //    listed once per (wall, direction); workgroups take chunks of the list
-//    and write per-chunk sums that k_wall_forces adds up per wall.
+//    and write per-chunk sums that the step kernel adds up per wall.
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -528,21 +528,6 @@ __global__ __launch_bounds__(kBlock) void k_links(LinkArgs a)
         wall_block<S>(a, b - a.nb, s_red);
 }
 
-// Wall w: the sum of its chunks' partial forces and torques.
-__global__ __launch_bounds__(64) void k_wall_forces(LinkArgs a)
-{
-    const int w = blockIdx.x, lane = threadIdx.x;
-    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int j = a.wl_wblk[w] + lane; j < a.wl_wblk[w + 1]; j += 64)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) v[c] += a.wl_part[6 * (size_t)j + c];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) v[c] += __shfl_xor(v[c], off);
-    if (lane < 6) a.out[6 * (a.nb + w) + lane] = v[lane];
-}
-
 // ---- reverse mode of the link pass ---------------------------------------
 //
 // Transpose of the boundary links for the gradient of the summed sphere
@@ -775,13 +760,6 @@ hipError_t launch_links(int storage, const LinkArgs &a, hipStream_t s)
     case 2: hipLaunchKernelGGL(k_links<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_wall_forces(const LinkArgs &a, hipStream_t s)
-{
-    if (a.n_walls <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_wall_forces, dim3(a.n_walls), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -177,9 +177,28 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int t)
     }
 }
 
+// Force and torque on wall w: the sum of its link-pass chunks, by the first
+// wavefront of a workgroup (lanes take every 64th chunk, then a fixed
+// butterfly), so the result does not depend on the launch.
+__device__ __forceinline__ void wall_total(const StepArgs &a, int w)
+{
+    const int lane = threadIdx.x;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int j = a.wsum_wblk[w] + lane; j < a.wsum_wblk[w + 1]; j += 64)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] += a.wsum_part[6 * (size_t)j + c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] += __shfl_xor(v[c], off);
+    if (lane < 6) a.wsum_out[6 * (a.wsum_nb + w) + lane] = v[lane];
+}
+
 template <int S, int TX, int TY, int TZ>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
 {
+    if (threadIdx.x < 64)
+        for (int w = blockIdx.x; w < a.n_wsum; w += gridDim.x) wall_total(a, w);
     tile_step<S, TX, TY, TZ>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
