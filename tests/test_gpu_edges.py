@@ -1,0 +1,87 @@
+"""Edge cases of the geometry on the GPU, against the FP64 oracle (same bars
+as the step: populations 1e-5 relative, forces and torques 1e-4
+norm-relative; owner maps bit for bit).
+
+* spheres large enough that their candidate links do not fit one list, so
+  the link pass takes them in rounds of box nodes;
+* overlapping spheres, a sphere overlapping a wall and spheres across the
+  periodic boundary (precedence: walls, then the lower sphere index);
+* a box a few nodes wide;
+* no solids at all.
+"""
+import numpy as np
+import pytest
+
+import lbm_workloads as W
+from ._pair import advance, force_rel_err, make_pair, pop_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(o, lat, pop_bar=1e-5, force_bar=1e-4):
+    np.testing.assert_array_equal(lat.get_owner(), o.owner())
+    pe = pop_rel_err(o, lat)
+    fe, te = force_rel_err(o, lat)
+    print(f"pop {pe:.2e}  F {fe:.2e}  T {te:.2e}")
+    assert pe <= pop_bar and fe <= force_bar and te <= force_bar
+
+
+def test_large_spheres_take_rounds(torch_stream):
+    rng = np.random.Generator(np.random.PCG64(21))
+    R = np.array([7.8, 9.5, 11.0])
+    X = np.array([[12.3, 14.1, 13.7], [36.6, 33.2, 15.4], [22.5, 30.8, 38.9]])
+    case = W.Case(name="large_spheres", nx=48, ny=48, nz=52, tau0=0.65, smag_c=0.12,
+                  body_force=(2e-6, 0.0, 0.0), X=X, V=rng.normal(0.0, 0.02, (3, 3)),
+                  Omega=rng.normal(0.0, 0.002, (3, 3)), R=R, u_init=rng.normal(0.0, 0.01, (3, 52, 48, 48)),
+                  drift=True)
+    o, lat = make_pair(case, stream=torch_stream)
+    advance(o, lat, case, 0, 20)
+    _check(o, lat)
+    lat.close()
+
+
+def test_overlaps_walls_and_periodic_images(torch_stream):
+    nx, ny, nz = 34, 30, 40
+    w = np.zeros((nz, ny, nx), np.uint8)
+    w[:, :, 0] = 1                  # wall 1: the plane x = 0 (moving along y)
+    w[20:23, 10:20, 14:18] = 2      # wall 2: a block, static
+    rng = np.random.Generator(np.random.PCG64(8))
+    X = np.array([[2.2, 15.3, 10.4],    # overlaps wall 1
+                  [8.1, 14.7, 11.2],    # overlaps sphere 0
+                  [16.2, 15.1, 21.6],   # overlaps the block
+                  [30.6, 0.7, 38.9],    # across three periodic boundaries
+                  [20.4, 27.9, 4.1]])
+    R = np.array([4.0, 4.5, 3.5, 3.2, 2.6])
+    case = W.Case(name="overlaps", nx=nx, ny=ny, nz=nz, tau0=0.7, smag_c=0.1, body_force=(1e-6, 0.0, 0.0),
+                  wall_id=w, wall_vel=np.array([[0.0, 0.01, 0.0], [0.0, 0.0, 0.0]]),
+                  wall_ref=np.array([[0.0, 15.0, 20.0], [16.0, 15.0, 21.5]]),
+                  X=X, V=rng.normal(0.0, 0.03, (5, 3)), Omega=rng.normal(0.0, 0.003, (5, 3)), R=R,
+                  u_init=rng.normal(0.0, 0.01, (3, nz, ny, nx)), drift=True)
+    o, lat = make_pair(case, stream=torch_stream)
+    np.testing.assert_array_equal(lat.get_owner(), o.owner())
+    advance(o, lat, case, 0, 25)
+    _check(o, lat)
+    lat.close()
+
+
+def test_box_a_few_nodes_wide(torch_stream):
+    rng = np.random.Generator(np.random.PCG64(5))
+    case = W.Case(name="tiny", nx=8, ny=9, nz=7, tau0=0.8, smag_c=0.1, body_force=(1e-6, 0.0, 0.0),
+                  X=np.array([[3.6, 4.2, 0.4]]), V=np.array([[0.05, -0.04, 0.03]]),
+                  Omega=np.array([[0.0, 0.01, 0.0]]), R=np.array([2.3]),
+                  u_init=rng.normal(0.0, 0.01, (3, 7, 9, 8)), drift=True)
+    o, lat = make_pair(case, stream=torch_stream)
+    advance(o, lat, case, 0, 30)
+    _check(o, lat)
+    lat.close()
+
+
+def test_no_solids(torch_stream):
+    case = W.case_box(n=(20, 12, 18), n_spheres=0, tau0=0.58, smag_c=0.18, body_force=(3e-6, -1e-6, 0.0),
+                      u_sigma=0.02, seed=11)
+    o, lat = make_pair(case, stream=torch_stream)
+    advance(o, lat, case, 0, 40)
+    _check(o, lat)
+    F, T = lat.get_forces()
+    assert F.shape == (0, 3) and T.shape == (0, 3)
+    lat.close()
