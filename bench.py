@@ -147,7 +147,7 @@ def main():
     import lbm_workloads as W
 
     torch.cuda.set_device(0)
-    case = W.case_c1(drift=not args.static)
+    case = W.case_piston_duct(drift=not args.static)
     K, Wm = args.steps, args.warmup
     main_run = timed_run(case, args.storage, K, Wm)
     copy_gbs = copy_bandwidth()

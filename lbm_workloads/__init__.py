@@ -33,7 +33,7 @@ from typing import Optional
 import numpy as np
 
 __all__ = [
-    "Case", "rsa_pack", "min_tie_gap", "case_c0", "case_duct", "case_c1", "case_adjoint",
+    "Case", "rsa_pack", "min_tie_gap", "case_box32", "case_duct", "case_piston_duct", "case_adjoint",
     "case_box", "drift_positions", "case_sweep_instances",
 ]
 
@@ -157,7 +157,7 @@ def rsa_pack(rng: np.random.Generator, radii: np.ndarray, lo, hi, gap: float,
     return centres
 
 
-def case_c0(seed: int = 0) -> Case:
+def case_box32(seed: int = 0) -> Case:
     """Small parity case: 32^3 periodic box, 8 fixed spheres of radius 4.
 
     BGK+Smagorinsky with C = 0.1, tau0 = 0.6, body force 1e-6 along x,
@@ -170,7 +170,7 @@ def case_c0(seed: int = 0) -> Case:
     R = np.full(8, 4.0)
     X = rsa_pack(rng, R, (0, 0, 0), (n, n, n), gap=2.0, box=(n, n, n))
     u = rng.normal(0.0, 0.01, size=(3, n, n, n))
-    return Case(name="c0_32cube_8spheres", nx=n, ny=n, nz=n, tau0=0.6, smag_c=0.1,
+    return Case(name="box_32cube_8spheres", nx=n, ny=n, nz=n, tau0=0.6, smag_c=0.1,
                 body_force=(1e-6, 0.0, 0.0), X=X, V=np.zeros((8, 3)),
                 Omega=np.zeros((8, 3)), R=R, u_init=u, steps=100)
 
@@ -218,7 +218,7 @@ def case_duct(nx=128, ny=128, nz=512, n_spheres=4000, r_min=2.0, r_max=6.0,
                 wall_ref=wall_ref, X=X, V=V, Omega=W, R=R, steps=steps, drift=drift)
 
 
-def case_c1(seed: int = 1, drift: bool = True) -> Case:
+def case_piston_duct(seed: int = 1, drift: bool = True) -> Case:
     """The full piston-duct slurry: 128x128x512, 4000 spheres, solid fraction 0.25."""
     return case_duct(seed=seed, drift=drift)
 

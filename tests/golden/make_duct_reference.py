@@ -36,7 +36,7 @@ def main():
     args = ap.parse_args()
     marks = sorted(int(s) for s in args.steps.split(","))
     oracle.set_threads(args.threads)
-    case = W.case_c1(drift=True)
+    case = W.case_piston_duct(drift=True)
     o = oracle.Oracle.from_case(case)
     rng = np.random.Generator(np.random.PCG64(11))
     out = {"steps": np.array(marks), "samples": np.array(SAMPLES)}

@@ -110,7 +110,7 @@ def test_version(P):
 
 
 def test_generators_deterministic():
-    a, b = W.case_c0(), W.case_c0()
+    a, b = W.case_box32(), W.case_box32()
     np.testing.assert_array_equal(a.X, b.X)
     np.testing.assert_array_equal(a.u_init, b.u_init)
     assert a.X.shape == (8, 3) and np.all(a.R == 4.0)

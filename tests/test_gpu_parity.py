@@ -20,13 +20,13 @@ pytestmark = pytest.mark.gpu
 POP_TOL = 1e-5
 FORCE_TOL = 1e-4
 
-_C1 = {}
+_DUCT = {}
 
 
-def _case_c1():
-    if "c" not in _C1:
-        _C1["c"] = W.case_c1()
-    return _C1["c"]
+def _piston_duct():
+    if "c" not in _DUCT:
+        _DUCT["c"] = W.case_piston_duct()
+    return _DUCT["c"]
 
 
 def _check(o, lat, pop_tol=POP_TOL, force_tol=FORCE_TOL):
@@ -39,16 +39,16 @@ def _check(o, lat, pop_tol=POP_TOL, force_tol=FORCE_TOL):
     return pe, fe, te
 
 
-def test_c0_parity_100_steps(torch_stream):
-    case = W.case_c0()
+def test_box32_parity_100_steps(torch_stream):
+    case = W.case_box32()
     o, lat = make_pair(case, stream=torch_stream)
     advance(o, lat, case, 0, 100)
     _check(o, lat)
     lat.close()
 
 
-def test_c0_halfway_parity(torch_stream):
-    case = W.case_c0()
+def test_box32_halfway_parity(torch_stream):
+    case = W.case_box32()
     o, lat = make_pair(case, halfway=True, stream=torch_stream)
     advance(o, lat, case, 0, 40)
     _check(o, lat)
@@ -167,7 +167,7 @@ def test_full_size_piston_duct_parity(torch_stream, halfway):
     configuration the benchmark times."""
     import oracle
     oracle.set_threads(16)
-    case = _case_c1()
+    case = _piston_duct()
     o, lat = make_pair(case, halfway=halfway, stream=torch_stream)
     advance(o, lat, case, 0, 3)
     _check(o, lat)

@@ -40,7 +40,7 @@ def _macro_err(o, lat):
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
-def test_c0_reduced_precision_error(storage, torch_stream):
+def test_box32_reduced_precision_error(storage, torch_stream):
     case = W.case_box()
     o, lat = make_pair(case, storage=storage, stream=torch_stream)
     advance(o, lat, case, 0, case.steps)
@@ -81,7 +81,7 @@ def test_duct_precision_statement(torch_stream):
     from paper_1703_05158_amd import Lattice
     ref = np.load(REF)
     marks = [int(s) for s in ref["steps"]]
-    case = W.case_c1(drift=True)
+    case = W.case_piston_duct(drift=True)
     nb = case.n_bodies
     tabs = torch.empty((marks[-1], nb, 10), dtype=torch.float64, device="cuda")
     for n in range(1, marks[-1] + 1):
