@@ -1012,7 +1012,6 @@ lbm_status lbm_drag_gradient(lbm_handle h, int32_t nsteps, int32_t ckpt, double 
     for (auto &b : ck) b = static_cast<float *>(get(popb));
     for (auto &b : seg) b = static_cast<float *>(get(popb));
     float *lam[2] = {static_cast<float *>(get(popb)), static_cast<float *>(get(popb))};
-    float *mu = static_cast<float *>(get(popb));
     const int nbt = std::max(nb + h->n_walls, 1);
     double *fscratch = static_cast<double *>(get(sizeof(double) * 6 * (size_t)nbt));
     double *accsave = static_cast<double *>(get(sizeof(double) * 6 * (size_t)nbt));
@@ -1068,17 +1067,21 @@ lbm_status lbm_drag_gradient(lbm_handle h, int32_t nsteps, int32_t ckpt, double 
         // steps m = k + 1 whose source P_k lies in the segment, m from N - 1 down
         for (int m = std::min(end, nsteps - 1); m >= start + 1; --m) {
             float *src = seg[(size_t)(m - 1 - start)];
-            LinkArgs la = link_args(h);
-            la.pop = src;
-            la.out = fscratch;
-            HIP_TRY(h, launch_links(c.storage, la, h->stream));  // link values of step m in src
+            if (m == end) {
+                // the recompute stopped before step end: put its link values
+                // into the solid slots of P_{end-1}; for earlier steps the
+                // recompute's own link pass left them there
+                LinkArgs la = link_args(h);
+                la.pop = src;
+                la.out = fscratch;
+                HIP_TRY(h, launch_links(c.storage, la, h->stream));
+            }
             StepArgs a = step_args(h);
             a.flag = nullptr;
             a.src = src;
-            AdjStepArgs ga{a, lam[li], mu, dF_tile};
+            AdjStepArgs ga{a, lam[li], lam[1 - li], dF_tile};
             HIP_TRY(h, launch_adj_collide(ga, h->stream));
-            HIP_TRY(h, launch_adj_stream(a, mu, lam[1 - li], h->stream));
-            AdjLinkArgs am{lg, mu, lam[1 - li], dV};
+            AdjLinkArgs am{lg, lam[1 - li], lam[1 - li], dV};
             HIP_TRY(h, launch_adj_links(am, h->stream));
             li = 1 - li;
         }

@@ -123,13 +123,14 @@ struct BatchLinkArgs {
 struct AdjStepArgs {
     StepArgs a;                   // src = the state P_{n-1} the step starts from
     const float *lam;             // adjoint of the post-collision state P_n, [19][Ns]
-    float *mu;                    // adjoint of the streamed populations f_n, [19][Ns]
+    float *lam_prev;              // adjoint of P_{n-1}, [19][Ns]: every entry is written (see k_adj_collide)
     double *dF_tile;              // [n_tiles][3], accumulated over the steps
 };
 
 struct AdjLinkArgs {
     LinkArgs a;                   // geometry and bodies; pop unused
-    const float *mu;              // adjoint of f_n, or null: the objective's own derivative
+    const float *mu;              // adjoint of f_n at the links, in the solid slots (p, I) of a
+                                  // [19][Ns] array; null: the objective's own derivative
     float *lam;                   // adjoint of P_{n-1}, links add into it
     double *dV;                   // [nb][3], accumulated over the steps
 };
@@ -160,7 +161,6 @@ hipError_t launch_batch_flip(int *cur, int n, hipStream_t s);
 
 hipError_t launch_zieb_update(int storage, const ZiebArgs &z, hipStream_t s);
 hipError_t launch_adj_collide(const AdjStepArgs &g, hipStream_t s);
-hipError_t launch_adj_stream(const StepArgs &a, const float *mu, float *lam, hipStream_t s);
 hipError_t launch_adj_links(const AdjLinkArgs &g, hipStream_t s);
 hipError_t launch_adj_reduce(const double *dF_tile, int n_tiles, double *dF, hipStream_t s);
 

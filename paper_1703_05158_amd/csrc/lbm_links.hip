@@ -598,7 +598,7 @@ __device__ __forceinline__ void adj_sphere_block(const AdjLinkArgs &g, int b, Sp
                     q = fminf(fmaxf(cc / (__builtin_sqrtf(disc) - bb), 0.0f), 1.0f);
                 }
                 const float ckx = (float)(-cx);
-                const float m = g.mu ? *at(g.mu + (size_t)I * Ns, xi) : ckx;
+                const float m = g.mu ? *at(g.mu + (size_t)I * Ns, pi) : ckx;
                 float ak, ab = 0.f, ai = 0.f, aw;
                 uint32_t bi = 0;
                 if (q < 0.5f) {

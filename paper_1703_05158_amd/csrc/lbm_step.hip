@@ -309,8 +309,13 @@ __global__ __launch_bounds__(1024) void k_zieb_update(ZiebArgs z)
 // For a step P_n = C(f_n), f_n = S(P_{n-1}), k_adj_collide turns the adjoint
 // lambda_n of P_n into the adjoint mu_n of the streamed populations f_n,
 // mu = (dC/df)^T lambda, node by node, and adds lambda . dC/dF (the body
-// force) to per-tile sums; k_adj_stream and the link kernel then apply the
-// transpose of the streaming S.  The collision is recomputed from f_n:
+// force) to per-tile sums.  It applies the transpose of plain streaming in
+// the same pass: f_n(x)[i] came from P_{n-1}(x - c_i)[i], so mu(x)[i] is
+// pushed to lambda_{n-1}(x - c_i)[i].  Streaming is a permutation, so every
+// entry of lambda_{n-1} is written once: solid nodes push zeros (nothing was
+// pulled from them), and where x - c_i is solid the pushed value is the
+// adjoint of a link value, which the link kernel then takes from that solid
+// slot and adds to the populations the link was formed from.  The collision is recomputed from f_n:
 // moments, the equilibrium, Pi, Q = Pi:Pi, tau* and the Guo source, as in
 // the forward step (Sec. 2.2); the derivative of sqrt(Q) is taken as
 // 1/(2 sqrt(Q + 1e-30)), finite where Q = 0.
@@ -451,10 +456,23 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjStepArgs ga)
         }
         collide_adjoint(a, g, lam, mu, Fb);
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) *at(ga.mu + (size_t)i * Ns, idx) = mu[i];
+        for (int i = 0; i < kQ; ++i) {
+            const int sx = CX[i] > 0 ? xm : (CX[i] < 0 ? xp : x);
+            const int sy = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
+            const int sz = CZ[i] > 0 ? zm : (CZ[i] < 0 ? zp : z);
+            *at(ga.lam_prev + (size_t)i * Ns, (uint32_t)(sx + nx * (sy + ny * sz))) = mu[i];
+        }
     } else if (in) {
+        const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+        const int yp = y + 1 == ny ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+        const int zp = z + 1 == nz ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) *at(ga.mu + (size_t)i * Ns, idx) = 0.0f;
+        for (int i = 0; i < kQ; ++i) {
+            const int sx = CX[i] > 0 ? xm : (CX[i] < 0 ? xp : x);
+            const int sy = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
+            const int sz = CZ[i] > 0 ? zm : (CZ[i] < 0 ? zp : z);
+            *at(ga.lam_prev + (size_t)i * Ns, (uint32_t)(sx + nx * (sy + ny * sz))) = 0.0f;
+        }
     }
     // body-force part: per-tile sums in a fixed order
     __shared__ double s_red[kBlock / 64][3];
@@ -470,37 +488,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjStepArgs ga)
         double v = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) v += s_red[w][tid];
         ga.dF_tile[3 * (size_t)t + tid] += v;
-    }
-}
-
-// Transpose of plain streaming: P_{n-1}(y)[i] went to f_n(y + c_i)[i] when
-// both nodes are fluid; boundary links add their parts afterwards.
-template <int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_adj_stream(StepArgs a, const float *mu, float *lam)
-{
-    const size_t Ns = (size_t)a.Ns;
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int tid = threadIdx.x;
-    const int t = xcd_remap(blockIdx.x, gridDim.x);
-    const int r = t / a.ntx;
-    const int x = (t - r * a.ntx) * TX + tid % TX;
-    const int y = (r % a.nty) * TY + (tid / TX) % TY;
-    const int z = (r / a.nty) * TZ + tid / (TX * TY);
-    if (x >= nx || y >= ny || z >= nz) return;
-    const uint32_t idx = (uint32_t)(x + nx * (y + ny * z));
-    const bool fluid = *at(a.own, idx) >= kVacated;
-    const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
-    const int yp = y + 1 == ny ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
-    const int zp = z + 1 == nz ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const int sx = CX[i] > 0 ? xp : (CX[i] < 0 ? xm : x);
-        const int sy = CY[i] > 0 ? yp : (CY[i] < 0 ? ym : y);
-        const int sz = CZ[i] > 0 ? zp : (CZ[i] < 0 ? zm : z);
-        const uint32_t d = (uint32_t)(sx + nx * (sy + ny * sz));   // y + c_i
-        float v = 0.0f;
-        if (fluid && *at(a.own, d) >= kVacated) v = *at(mu + (size_t)i * Ns, d);
-        *at(lam + (size_t)i * Ns, idx) = v;
     }
 }
 
@@ -576,18 +563,6 @@ hipError_t launch_adj_collide(const AdjStepArgs &g, hipStream_t s)
     case kTile32x4x2: hipLaunchKernelGGL((k_adj_collide<32, 4, 2>), dim3(g.a.n_tiles), dim3(kBlock), 0, s, g); break;
     case kTile32x2x4: hipLaunchKernelGGL((k_adj_collide<32, 2, 4>), dim3(g.a.n_tiles), dim3(kBlock), 0, s, g); break;
     case kTile16x8x2: hipLaunchKernelGGL((k_adj_collide<16, 8, 2>), dim3(g.a.n_tiles), dim3(kBlock), 0, s, g); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_adj_stream(const StepArgs &a, const float *mu, float *lam, hipStream_t s)
-{
-    switch (a.tile) {
-    case kTile64x2x2: hipLaunchKernelGGL((k_adj_stream<64, 2, 2>), dim3(a.n_tiles), dim3(kBlock), 0, s, a, mu, lam); break;
-    case kTile32x4x2: hipLaunchKernelGGL((k_adj_stream<32, 4, 2>), dim3(a.n_tiles), dim3(kBlock), 0, s, a, mu, lam); break;
-    case kTile32x2x4: hipLaunchKernelGGL((k_adj_stream<32, 2, 4>), dim3(a.n_tiles), dim3(kBlock), 0, s, a, mu, lam); break;
-    case kTile16x8x2: hipLaunchKernelGGL((k_adj_stream<16, 8, 2>), dim3(a.n_tiles), dim3(kBlock), 0, s, a, mu, lam); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
