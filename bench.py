@@ -87,6 +87,35 @@ def cpu_baseline(case, sample_steps, threads):
                               "sample": f"1 drift step on 1 thread, {dt1:.1f} s"}}
 
 
+def box32_run(threads, steps=100):
+    """The 32^3 parity box (8 spheres, 100 steps) on the GPU and on the FP64
+    oracle, for the record: 32 k nodes are far too few to load the GPU, and
+    the whole state fits in its last-level cache."""
+    import torch
+
+    import lbm_workloads as W
+    import oracle
+    from paper_1703_05158_amd import Lattice
+
+    case = W.case_box32()
+    lat = Lattice.from_case(case, stream=torch.cuda.current_stream().cuda_stream)
+    lat.step(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lat.close()
+    oracle.set_threads(threads)
+    o = oracle.Oracle.from_case(case)
+    t1 = time.perf_counter()
+    o.step(steps)
+    dto = time.perf_counter() - t1
+    return {"workload": "box_32cube_8spheres", "steps": steps,
+            "gpu_mlups": round(case.n_nodes * steps / dt / 1e6, 1),
+            "oracle_mlups": round(case.n_nodes * steps / dto / 1e6, 2), "oracle_threads": threads}
+
+
 def copy_bandwidth():
     """Device-to-device copy of 1 GiB (read + write), GB/s: the practical
     bandwidth reference beside the HBM peak."""
@@ -164,6 +193,7 @@ def main():
                    "per_step": "set_bodies_device + step + get_forces_device" if case.drift
                    else "step + get_forces_device"},
         "mflups": main_run["mflups"],
+        "ms_per_step_median5": main_run["ms_per_step_median5"],
         "ms_per_step_host_forces": main_run["ms_per_step_host_forces"],
         "roofline": main_run["roofline"],
     }
@@ -185,6 +215,8 @@ def main():
         out["batched_sweep"] = sweep_run(args.sweep_steps)
     if args.adjoint and args.storage == "f32" and not args.static:
         out["adjoint"] = adjoint_run()
+    if args.cpu_steps > 0 and not args.static:
+        out["box32"] = box32_run(args.cpu_threads)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps, args.cpu_threads)
         out["cpu_baseline"]["gpu_over_oracle"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
@@ -288,9 +320,11 @@ def timed_run(case, storage, K, Wm):
     # per-step kinematics, resident in HBM before timing (the DEM's output)
     tabs = None
     K2 = min(K, 50)
+    nr = max(K // 5, 1)
+    nt = Wm + K + 5 * nr + K2
     if case.drift:
-        tabs = torch.empty((Wm + K + K2, nb, 10), dtype=torch.float64, device="cuda")
-        for n in range(1, Wm + K + K2 + 1):
+        tabs = torch.empty((nt, nb, 10), dtype=torch.float64, device="cuda")
+        for n in range(1, nt + 1):
             X, V, Om, R = case.bodies_at(n)
             tabs[n - 1] = torch.from_numpy(np.concatenate([X, V, Om, R[:, None]], 1))
     hist = torch.zeros((K, nbt, 6), dtype=torch.float64, device="cuda")
@@ -317,12 +351,24 @@ def timed_run(case, storage, K, Wm):
     lat.profile(False)
     n_fluid_end = lat.count_fluid()
     assert torch.isfinite(hist).all().item()
+    # five more repetitions of K/5 steps each, for a median
+    reps = []
+    for r in range(5):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for n in range(nr):
+            if tabs is not None:
+                lat.set_bodies_device(nb, tabs[Wm + K + r * nr + n])
+            lat.step(1)
+            lat.get_forces_device(hist[n])
+        torch.cuda.synchronize()
+        reps.append((time.perf_counter() - t1) / nr)
     # K2 more steps with the forces copied to the host after every step
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for n in range(K2):
         if tabs is not None:
-            lat.set_bodies_device(nb, tabs[Wm + K + n])
+            lat.set_bodies_device(nb, tabs[Wm + K + 5 * nr + n])
         lat.step(1)
         lat.get_forces()
     dt_host = time.perf_counter() - t0
@@ -343,6 +389,7 @@ def timed_run(case, storage, K, Wm):
             "kernel": f"k_step<{storage}>", "kernel_ms": round(k_avg_s * 1e3, 4),
             "alg_bytes_per_launch": int(alg_bytes)}
     return {"value": round(N * K / dt / 1e6, 1), "ms_per_step": round(dt / K * 1e3, 4),
+            "ms_per_step_median5": round(float(np.median(reps)) * 1e3, 4),
             "ms_per_step_host_forces": round(dt_host / K2 * 1e3, 4),
             "mflups": round(nf * K / dt / 1e6, 1), "fluid_nodes": int(nf), "roofline": roof}
 
