@@ -336,6 +336,10 @@ def timed_run(case, storage, K, Wm):
         lat.step(1)
     torch.cuda.synchronize()
     n_fluid = lat.count_fluid()
+    # the step kernel's tile shape for this box (timed launches that leave
+    # the state as it is)
+    from paper_1703_05158_amd import TILE_SHAPES
+    shape, shape_us = lat.autotune(trial_steps=10)
 
     lat.profile(True)
     torch.cuda.synchronize()
@@ -387,6 +391,7 @@ def timed_run(case, storage, K, Wm):
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
             "kernel": f"k_step<{storage}>", "kernel_ms": round(k_avg_s * 1e3, 4),
+            "tile": TILE_SHAPES[shape], "tile_us": {TILE_SHAPES[i]: round(float(t), 1) for i, t in enumerate(shape_us)},
             "alg_bytes_per_launch": int(alg_bytes)}
     return {"value": round(N * K / dt / 1e6, 1), "ms_per_step": round(dt / K * 1e3, 4),
             "ms_per_step_median5": round(float(np.median(reps)) * 1e3, 4),
