@@ -259,7 +259,7 @@ lbm_status lbm_set_body_force(lbm_handle h, const double *F);
  * J; dJdF[3] = dJ/d(body force); dJdV[3 n_bodies] = dJ/dV_b, sphere-major
  * (may be NULL with no spheres).  The square root of Q = Pi:Pi has the
  * derivative 1/(2 sqrt(Q + 1e-30)).  Device memory: ceil(nsteps/ckpt) +
- * min(ckpt, nsteps) + 3 population buffers, allocated for the call.  Needs
+ * min(ckpt, nsteps) + 2 population buffers, allocated for the call.  Needs
  * FP32 storage, no walls and no inflow plane.  Synchronises.  Errors: ARG,
  * STATE, OOM, HIP. */
 lbm_status lbm_drag_gradient(lbm_handle h, int32_t nsteps, int32_t ckpt, double *J, double *dJdF,
