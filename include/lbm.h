@@ -134,8 +134,9 @@ lbm_status lbm_set_walls(lbm_handle h, const uint8_t *wall_id, int32_t n_walls,
  * nodes that turn from solid to fluid are refilled with the equilibrium at
  * rho0 and the velocity they had as solids.  The copy is asynchronous on the
  * handle's stream (pinned staging).  The link pass takes the spheres in
- * Morton order of the centres given here (kept for later device tables of
- * the same count); no result depends on that order.  Errors: ARG (null with
+ * Morton order of centres given here (made again when the count changes and
+ * on every 32nd call, kept for device tables of the same count); no result
+ * depends on that order.  Errors: ARG (null with
  * n > 0, ranges, non-finite values), CAPACITY (n > max_bodies). */
 lbm_status lbm_set_bodies(lbm_handle h, int32_t n, const double *X, const double *V,
                           const double *Omega, const double *R);

@@ -61,6 +61,7 @@ struct lbm_ctx {
     int *order = nullptr;              // max_bodies: sphere order of the link pass (Morton order of the centres)
     int *order_pin = nullptr;          // its host staging
     int n_order = 0;                   // body count the order was made for (0: none)
+    int order_age = 0;                 // host body tables staged since the order was made
     hipEvent_t stage_evt = nullptr;
     bool initialized = false;
     int steps_done = 0;
@@ -528,30 +529,45 @@ lbm_status lbm_set_walls(lbm_handle h, const uint8_t *wall_id, int32_t n_walls, 
     return rasterize_full(h);
 }
 
+// The low 21 bits of v spread to every third bit.
+static uint64_t spread3(uint64_t v)
+{
+    v &= 0x1FFFFF;
+    v = (v | v << 32) & 0x1F00000000FFFFull;
+    v = (v | v << 16) & 0x1F0000FF0000FFull;
+    v = (v | v << 8) & 0x100F00F00F00F00Full;
+    v = (v | v << 4) & 0x10C30C30C30C30C3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+}
+
 // Interleaved bits of the centre's cell (8 nodes a side) on each axis.
 static uint64_t morton_key(const double *X)
 {
-    uint64_t key = 0;
-    for (int a = 0; a < 3; ++a) {
-        const uint64_t c = (uint64_t)(X[a] / 8.0) & 0xFFFFF;
-        for (int bit = 0; bit < 20; ++bit) key |= ((c >> bit) & 1u) << (3 * bit + a);
-    }
-    return key;
+    return spread3((uint64_t)(X[0] / 8.0)) | spread3((uint64_t)(X[1] / 8.0)) << 1 |
+           spread3((uint64_t)(X[2] / 8.0)) << 2;
 }
 
 static lbm_status stage_bodies(lbm_ctx *h, int32_t n)
 {
     // the link pass takes the spheres in Morton order of their centres, so
     // that the workgroups on one XCD work on neighbouring spheres, which
-    // share population lines; the order does not change any result
-    std::vector<std::pair<uint64_t, int>> keys((size_t)n);
-    for (int b = 0; b < n; ++b) keys[(size_t)b] = {morton_key(h->pinned + (size_t)b * kBodyStride), b};
-    std::sort(keys.begin(), keys.end());
-    for (int b = 0; b < n; ++b) h->order_pin[b] = keys[(size_t)b].second;
+    // share population lines.  The order changes no result, and spheres move
+    // little between calls: it is made again when the count changes, else
+    // every 32nd call.
     HIP_TRY(h, hipMemcpyAsync(h->tab[1 - h->ts], h->pinned, sizeof(double) * kBodyStride * (size_t)n,
                               hipMemcpyHostToDevice, h->stream));
-    if (n > 0) HIP_TRY(h, hipMemcpyAsync(h->order, h->order_pin, sizeof(int) * (size_t)n, hipMemcpyHostToDevice, h->stream));
-    h->n_order = n;
+    if (n != h->n_order || ++h->order_age >= 32) {
+        std::vector<std::pair<uint64_t, int>> keys((size_t)n);
+        for (int b = 0; b < n; ++b) keys[(size_t)b] = {morton_key(h->pinned + (size_t)b * kBodyStride), b};
+        std::sort(keys.begin(), keys.end());
+        for (int b = 0; b < n; ++b) h->order_pin[b] = keys[(size_t)b].second;
+        if (n > 0)
+            HIP_TRY(h, hipMemcpyAsync(h->order, h->order_pin, sizeof(int) * (size_t)n, hipMemcpyHostToDevice,
+                                      h->stream));
+        h->n_order = n;
+        h->order_age = 0;
+    }
     HIP_TRY(h, hipEventRecord(h->stage_evt, h->stream));
     h->nb_next = n;
     h->dirty = true;
