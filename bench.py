@@ -390,6 +390,8 @@ def timed_run(case, storage, K, Wm):
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
+            "frac_measured": None if traffic is None else round(traffic / k_avg_s / 1e9 / HBM_PEAK_GBS, 4),
+            "kernel_mlups": round(N / k_avg_s / 1e6, 1),
             "kernel": f"k_step<{storage}>", "kernel_ms": round(k_avg_s * 1e3, 4),
             "tile": TILE_SHAPES[shape], "tile_us": {TILE_SHAPES[i]: round(float(t), 1) for i, t in enumerate(shape_us)},
             "alg_bytes_per_launch": int(alg_bytes)}
