@@ -93,7 +93,9 @@ def _box(case_or_dims):
 def drift_positions(case: Case, n: int) -> np.ndarray:
     """Centres after ``n`` steps of free drift, wrapped into the periodic box."""
     box = _box(case)
-    return np.mod(case.X + n * case.V, box)
+    P = np.mod(case.X + n * case.V, box)
+    # a tiny negative coordinate wraps to box - tiny, which can round to box
+    return np.where(P >= box, 0.0, P)
 
 
 def min_tie_gap(X: np.ndarray, R: np.ndarray, box) -> float:

@@ -665,6 +665,9 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
     StepArgs a = step_args(h);
     LinkArgs la = link_args(h);
     for (int s = 0; s < nsteps; ++s) {
+        // the inflow plane's mean velocity is that of the current state, on
+        // its own geometry: taken before the spheres of this step are drawn
+        if (h->zieb_z >= 0) HIP_TRY(h, launch_zieb_update(c.storage, zieb_args(h), h->stream));
         if (h->dirty && (st = rasterize_update(h)) != LBM_OK) return st;
         la.n_walls = h->n_walls;
         la.n_wblk = h->n_walls > 0 ? h->n_wblk : 0;
@@ -672,7 +675,6 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
         la.order = h->n_order == h->nb_state ? h->order : nullptr;
         la.bodies = h->tab[h->ts];
         la.pop = h->pop[h->cur];
-        if (h->zieb_z >= 0) HIP_TRY(h, launch_zieb_update(c.storage, zieb_args(h), h->stream));
         HIP_TRY(h, launch_links(c.storage, la, h->stream));
         // the step kernel's first workgroups add up the wall chunks
         a.n_wsum = la.n_walls;

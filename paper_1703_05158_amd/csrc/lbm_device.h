@@ -139,17 +139,25 @@ __device__ __forceinline__ double eq_dev(int i, double rho0, double u0, double u
 
 // |p - X|^2 with the minimum image, as a plain product-sum evaluated left to
 // right without fused multiply-add (the owner test compares it with R^2).
+// The products and sums are written here, under contraction off: the
+// compiler would otherwise fuse them into FMAs (as it does with __dmul_rn and
+// __dadd_rn, which are ordinary operations in device code), and a node
+// exactly on a sphere's surface would be decided differently.
 __device__ __forceinline__ double dist2(const double *B, int px, int py, int pz, int nx, int ny, int nz)
 {
+#pragma clang fp contract(off)
     const double dx = min_image((double)px - B[0], nx);
     const double dy = min_image((double)py - B[1], ny);
     const double dz = min_image((double)pz - B[2], nz);
-    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    const double sxy = dx * dx + dy * dy;
+    return sxy + dz * dz;
 }
 
 __device__ __forceinline__ bool inside(const double *B, int px, int py, int pz, int nx, int ny, int nz)
 {
-    return dist2(B, px, py, pz, nx, ny, nz) <= __dmul_rn(B[9], B[9]);
+#pragma clang fp contract(off)
+    const double r2 = B[9] * B[9];
+    return dist2(B, px, py, pz, nx, ny, nz) <= r2;
 }
 
 // Integer box holding every node of a sphere (grown by `pad` nodes).

@@ -85,3 +85,36 @@ def test_no_solids(torch_stream):
     F, T = lat.get_forces()
     assert F.shape == (0, 3) and T.shape == (0, 3)
     lat.close()
+
+
+def test_surface_ties_decided_like_the_oracle(torch_stream):
+    """Centres on a 0.1 grid and radii on a 0.5 grid put many nodes exactly,
+    or within an ulp, on a sphere surface.  The owner test is an FP64
+    product-sum without fused multiply-add on both sides, so the owner maps
+    agree node for node: fresh, and after drift steps that vacate and stamp
+    (velocities on a 0.1 grid as well)."""
+    import oracle
+    from paper_1703_05158_amd import Lattice
+    rng = np.random.Generator(np.random.PCG64(17))
+    nx, ny, nz = 40, 36, 44
+    n = 60
+    X = np.round(rng.uniform(0, 1, (n, 3)) * [nx, ny, nz], 1) % [nx, ny, nz]
+    R = rng.integers(4, 10, n) * 0.5
+    V = rng.integers(-3, 4, (n, 3)) * 0.1
+    case = W.Case(name="ties", nx=nx, ny=ny, nz=nz, tau0=0.7, smag_c=0.1, X=X, V=V,
+                  Omega=np.zeros((n, 3)), R=R, drift=True)
+    # the first centre gives an exact tie at node (6, 9, 4) with R = 3
+    case.X[0] = [8.4, 7.2, 4.6 - 0.6]
+    case.R[0] = 3.0
+    o = oracle.Oracle.from_case(case)
+    lat = Lattice.from_case(case, stream=torch_stream)
+    np.testing.assert_array_equal(lat.get_owner(), o.owner())
+    assert o.owner()[4, 9, 6] == 0
+    for step in range(1, 6):
+        Xs, Vs, Os, Rs = case.bodies_at(step)
+        o.set_bodies(Xs, Vs, Os, Rs)
+        lat.set_bodies(Xs, Vs, Os, Rs)
+        o.step(1)
+        lat.step(1)
+        np.testing.assert_array_equal(lat.get_owner(), o.owner())
+    lat.close()

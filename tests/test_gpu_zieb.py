@@ -95,3 +95,40 @@ def test_zieb_rejects_bad_planes(torch_stream):
     with pytest.raises(LBMError):
         Batch([lat])
     lat.close()
+
+
+def test_zieb_with_spheres_crossing_the_plane(torch_stream):
+    """Drifting spheres next to the plane cover and uncover plane nodes: the
+    plane mean, the density update and the redistribution then run over a
+    changing set of fluid nodes, on both sides."""
+    import dataclasses
+
+    import oracle
+    from paper_1703_05158_amd import Lattice
+    case, zp = _case()
+    X = np.array([[8.0, 7.0, 4.6], [16.0, 12.5, 5.2], [12.0, 9.0, 14.0]])
+    V = np.array([[0.02, 0.01, -0.03], [-0.01, 0.02, -0.035], [0.0, 0.0, 0.01]])
+    case = dataclasses.replace(case, X=X, V=V, R=np.array([3.0, 2.5, 3.5]), drift=True)
+    o = oracle.Oracle.from_case(case, init=False)
+    o.set_zieb(*zp)
+    o.init_fields(case.rho_init, case.u_init)
+    lat = Lattice.from_case(case, stream=torch_stream, init=False)
+    lat.set_zieb(*zp)
+    lat.init_fields(case.rho_init, case.u_init)
+    covered = []
+    for n in range(1, 61):
+        Xn, Vn, On, Rn = case.bodies_at(n)
+        o.set_bodies(Xn, Vn, On, Rn)
+        lat.set_bodies(Xn, Vn, On, Rn)
+        o.step(1)
+        lat.step(1)
+        covered.append(int((o.owner()[1] >= 0).sum()))
+    np.testing.assert_array_equal(lat.get_owner(), o.owner())
+    pe = pop_rel_err(o, lat)
+    fe, te = force_rel_err(o, lat)
+    rho, H, vf = lat.zieb_state()
+    print(f"pop {pe:.2e} F {fe:.2e} T {te:.2e} rho {rho:.8f} ({o.zieb['rho']:.8f}); plane solid nodes {covered[0]}..{max(covered)}")
+    assert max(covered) > min(covered)   # the plane's solid set changed
+    assert pe <= 1e-5 and fe <= 1e-4 and te <= 1e-4
+    assert rho == pytest.approx(o.zieb["rho"], rel=1e-6)
+    lat.close()
