@@ -29,12 +29,69 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 METRIC = "MLUPS and % of HBM roofline; mixed-precision vs FP32 at stated error"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_piston_duct_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1703_05158_amd", "csrc", "lbm_step.hip")
+# the step kernel's source and the headers it is compiled with
+KERNEL_SRC = [os.path.join(ROOT, "paper_1703_05158_amd", "csrc", f)
+              for f in ("lbm_step.hip", "lbm_device.h", "lbm_internal.h")]
+TRAFFIC_WORKLOAD = "piston_duct_128x128x512_4000spheres_drift"
 REFERENCE = os.path.join(ROOT, "tests", "golden", "duct_reference.npz")
 
 
 def kernel_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _counter_means(d):
+    """Mean counter value per dispatch of every kernel, from a rocprofv3
+    --pmc CSV output directory."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(d, "**", "run_counter_collection.csv"), recursive=True)
+    if len(f) != 1:
+        raise SystemExit(f"expected one run_counter_collection.csv under {d}, found {len(f)}")
+    per = {}
+    for r in csv.DictReader(open(f[0])):
+        per.setdefault(r["Kernel_Name"], {}).setdefault(r["Dispatch_Id"], 0.0)
+        per[r["Kernel_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    return {k: sum(v.values()) / len(v) for k, v in per.items()}
+
+
+def record_traffic(d):
+    """Write the step kernel's HBM bytes per launch from rocprofv3 counter
+    runs under d: pc_fetch and pc_write (FETCH_SIZE and WRITE_SIZE of the
+    --calibrate-copy run), pb_fetch_<s> and pb_write_<s> (the same counters
+    of --steps 4 --warmup 2 --cpu-steps 0 --no-mixed --no-sweep --no-adjoint
+    --storage <s>, for s in f32 and f16).  Each counter (KiB per dispatch) is
+    scaled by what it reads for a copy of 1 GiB read and 1 GiB written."""
+    import re
+    gib = 1 << 30
+    copy_f = max(v for k, v in _counter_means(os.path.join(d, "pc_fetch")).items() if "copyBuffer" in k)
+    copy_w = max(v for k, v in _counter_means(os.path.join(d, "pc_write")).items() if "copyBuffer" in k)
+    fs, ws = gib / 1024 / copy_f, gib / 1024 / copy_w
+    cmd = ("rocprofv3 --pmc {c} --output-format csv -d <out> -o run -- python3 <repo>/bench.py --steps 4 "
+           "--warmup 2 --cpu-steps 0 --no-mixed --no-sweep --no-adjoint --storage {s}")
+    out = {}
+    for st, sv in (("f32", 0), ("f16", 1)):
+        vals = []
+        for c in ("fetch", "write"):
+            m = {k: v for k, v in _counter_means(os.path.join(d, f"pb_{c}_{st}")).items()
+                 if re.search(rf"k_step<{sv},", k)}
+            if len(m) != 1:
+                raise SystemExit(f"expected one k_step<{sv},...> kernel in pb_{c}_{st}, found {list(m)}")
+            vals.append(next(iter(m.items())))
+        (kn, fk), (_, wk) = vals
+        g = re.search(r"k_step<(\d+), (\d+), (\d+), (\d+)>", kn).groups()
+        out[st] = {"kernel": "k_step<" + ",".join(g) + ">", "kernel_sha": kernel_sha(),
+                   "workload": TRAFFIC_WORKLOAD,
+                   "fetch_kib_per_dispatch": round(fk, 1), "write_kib_per_dispatch": round(wk, 1),
+                   "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+                   "bytes_per_launch": round(fk * 1024 * fs + wk * 1024 * ws),
+                   "commands": [cmd.format(c="FETCH_SIZE", s=st), cmd.format(c="WRITE_SIZE", s=st)]}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def measured_traffic(storage):
@@ -154,7 +211,12 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("OMP_NUM_THREADS", "16")))
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter scale reference)")
+    ap.add_argument("--record-traffic", metavar="DIR",
+                    help="write the step kernel's HBM bytes per launch from rocprofv3 counter runs under DIR")
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(args.record_traffic)
+        return
     if args.calibrate_copy:
         import torch
         torch.cuda.set_device(0)
