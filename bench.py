@@ -43,9 +43,9 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
-def _counter_means(d):
-    """Mean counter value per dispatch of every kernel, from a rocprofv3
-    --pmc CSV output directory."""
+def _counters(d):
+    """Counter value of every dispatch of every kernel, {kernel: {dispatch:
+    value}}, from a rocprofv3 --pmc CSV output directory."""
     import csv
     import glob
     f = glob.glob(os.path.join(d, "**", "run_counter_collection.csv"), recursive=True)
@@ -55,7 +55,12 @@ def _counter_means(d):
     for r in csv.DictReader(open(f[0])):
         per.setdefault(r["Kernel_Name"], {}).setdefault(r["Dispatch_Id"], 0.0)
         per[r["Kernel_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
-    return {k: sum(v.values()) / len(v) for k, v in per.items()}
+    return per
+
+
+def _copy_kib(d):
+    """The counter of the largest copy dispatch (the 1 GiB copy)."""
+    return max(v for k, per in _counters(d).items() if "copyBuffer" in k for v in per.values())
 
 
 def record_traffic(d):
@@ -63,12 +68,13 @@ def record_traffic(d):
     runs under d: pc_fetch and pc_write (FETCH_SIZE and WRITE_SIZE of the
     --calibrate-copy run), pb_fetch_<s> and pb_write_<s> (the same counters
     of --steps 4 --warmup 2 --cpu-steps 0 --no-mixed --no-sweep --no-adjoint
-    --storage <s>, for s in f32 and f16).  Each counter (KiB per dispatch) is
-    scaled by what it reads for a copy of 1 GiB read and 1 GiB written."""
+    --storage <s>, for s in f32 and f16).  Each counter (KiB per dispatch,
+    the mean over the step kernel's dispatches) is scaled by what it reads
+    for a copy of 1 GiB read and 1 GiB written."""
     import re
     gib = 1 << 30
-    copy_f = max(v for k, v in _counter_means(os.path.join(d, "pc_fetch")).items() if "copyBuffer" in k)
-    copy_w = max(v for k, v in _counter_means(os.path.join(d, "pc_write")).items() if "copyBuffer" in k)
+    copy_f = _copy_kib(os.path.join(d, "pc_fetch"))
+    copy_w = _copy_kib(os.path.join(d, "pc_write"))
     fs, ws = gib / 1024 / copy_f, gib / 1024 / copy_w
     cmd = ("rocprofv3 --pmc {c} --output-format csv -d <out> -o run -- python3 <repo>/bench.py --steps 4 "
            "--warmup 2 --cpu-steps 0 --no-mixed --no-sweep --no-adjoint --storage {s}")
@@ -76,7 +82,7 @@ def record_traffic(d):
     for st, sv in (("f32", 0), ("f16", 1)):
         vals = []
         for c in ("fetch", "write"):
-            m = {k: v for k, v in _counter_means(os.path.join(d, f"pb_{c}_{st}")).items()
+            m = {k: sum(v.values()) / len(v) for k, v in _counters(os.path.join(d, f"pb_{c}_{st}")).items()
                  if re.search(rf"k_step<{sv},", k)}
             if len(m) != 1:
                 raise SystemExit(f"expected one k_step<{sv},...> kernel in pb_{c}_{st}, found {list(m)}")
