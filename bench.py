@@ -68,9 +68,11 @@ def record_traffic(d):
     runs under d: pc_fetch and pc_write (FETCH_SIZE and WRITE_SIZE of the
     --calibrate-copy run), pb_fetch_<s> and pb_write_<s> (the same counters
     of --steps 4 --warmup 2 --cpu-steps 0 --no-mixed --no-sweep --no-adjoint
-    --storage <s>, for s in f32 and f16).  Each counter (KiB per dispatch,
-    the mean over the step kernel's dispatches) is scaled by what it reads
-    for a copy of 1 GiB read and 1 GiB written."""
+    --storage <s>, for s in f32 and f16).  The bench's tile autotuner runs
+    every tile shape of the step kernel on the workload, so each shape gets
+    its own figure.  Each counter (KiB per dispatch, the mean over that
+    kernel's dispatches) is scaled by what it reads for a copy of 1 GiB read
+    and 1 GiB written."""
     import re
     gib = 1 << 30
     copy_f = _copy_kib(os.path.join(d, "pc_fetch"))
@@ -80,29 +82,34 @@ def record_traffic(d):
            "--warmup 2 --cpu-steps 0 --no-mixed --no-sweep --no-adjoint --storage {s}")
     out = {}
     for st, sv in (("f32", 0), ("f16", 1)):
-        vals = []
+        per = []
         for c in ("fetch", "write"):
-            m = {k: sum(v.values()) / len(v) for k, v in _counters(os.path.join(d, f"pb_{c}_{st}")).items()
-                 if re.search(rf"k_step<{sv},", k)}
-            if len(m) != 1:
-                raise SystemExit(f"expected one k_step<{sv},...> kernel in pb_{c}_{st}, found {list(m)}")
-            vals.append(next(iter(m.items())))
-        (kn, fk), (_, wk) = vals
-        g = re.search(r"k_step<(\d+), (\d+), (\d+), (\d+)>", kn).groups()
-        out[st] = {"kernel": "k_step<" + ",".join(g) + ">", "kernel_sha": kernel_sha(),
-                   "workload": TRAFFIC_WORKLOAD,
-                   "fetch_kib_per_dispatch": round(fk, 1), "write_kib_per_dispatch": round(wk, 1),
+            m = {}
+            for k, v in _counters(os.path.join(d, f"pb_{c}_{st}")).items():
+                g = re.search(rf"k_step<{sv}, (\d+), (\d+), (\d+)>", k)
+                if g:
+                    m["x".join(g.groups())] = sum(v.values()) / len(v)
+            per.append(m)
+        tiles = sorted(set(per[0]) & set(per[1]))
+        if not tiles:
+            raise SystemExit(f"no k_step<{sv},...> kernel in both pb_fetch_{st} and pb_write_{st}")
+        out[st] = {"kernel_sha": kernel_sha(), "workload": TRAFFIC_WORKLOAD,
                    "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
-                   "bytes_per_launch": round(fk * 1024 * fs + wk * 1024 * ws),
-                   "commands": [cmd.format(c="FETCH_SIZE", s=st), cmd.format(c="WRITE_SIZE", s=st)]}
+                   "commands": [cmd.format(c="FETCH_SIZE", s=st), cmd.format(c="WRITE_SIZE", s=st)],
+                   "tiles": {t: {"kernel": f"k_step<{sv},{t.replace('x', ',')}>",
+                                 "fetch_kib_per_dispatch": round(per[0][t], 1),
+                                 "write_kib_per_dispatch": round(per[1][t], 1),
+                                 "bytes_per_launch": round(per[0][t] * 1024 * fs + per[1][t] * 1024 * ws)}
+                             for t in tiles}}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
 
 
-def measured_traffic(storage):
-    """HBM bytes per step-kernel launch from committed rocprofv3 counters,
-    only if they were taken on the current kernel source."""
+def measured_traffic(storage, tile):
+    """HBM bytes per launch of the step kernel with this tile shape
+    ("64x2x2", ...) from committed rocprofv3 counters, only if they were
+    taken on the current kernel source."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -110,7 +117,7 @@ def measured_traffic(storage):
     rec = d.get(storage)
     if not rec or rec.get("kernel_sha") != kernel_sha():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("tiles", {}).get(tile, {}).get("bytes_per_launch")
 
 
 def cpu_model():
@@ -454,7 +461,7 @@ def timed_run(case, storage, K, Wm):
     alg_bytes = 2 * 19 * sbytes * nf + 2 * N
     k_avg_s = kms / launches * 1e-3
     achieved = alg_bytes / k_avg_s / 1e9
-    traffic = measured_traffic(storage)
+    traffic = measured_traffic(storage, TILE_SHAPES[shape])
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),

@@ -43,30 +43,45 @@ def test_record_traffic_scales_by_the_copy(bench, tmp_path):
     _csv(tmp_path / "pb_write_f16", [(step16, 1, 4.0)])
     bench.record_traffic(str(tmp_path))
     rec = json.load(open(bench.TRAFFIC_FILE))
-    assert rec["f32"]["kernel"] == "k_step<0,64,2,2>" and rec["f16"]["kernel"] == "k_step<1,32,4,2>"
+    assert rec["f32"]["tiles"]["64x2x2"]["kernel"] == "k_step<0,64,2,2>"
+    assert rec["f16"]["tiles"]["32x4x2"]["kernel"] == "k_step<1,32,4,2>"
     assert rec["f32"]["fetch_scale"] == pytest.approx(2.0) and rec["f32"]["write_scale"] == pytest.approx(1.0)
     # mean over dispatches: fetch 200 KiB x 2, write 50 KiB x 1
-    assert rec["f32"]["bytes_per_launch"] == 200 * 1024 * 2 + 50 * 1024
-    assert rec["f16"]["bytes_per_launch"] == 10 * 1024 * 2 + 4 * 1024
-    assert bench.measured_traffic("f32") == rec["f32"]["bytes_per_launch"]
-    assert bench.measured_traffic("bf16") is None
+    assert rec["f32"]["tiles"]["64x2x2"]["bytes_per_launch"] == 200 * 1024 * 2 + 50 * 1024
+    assert rec["f16"]["tiles"]["32x4x2"]["bytes_per_launch"] == 10 * 1024 * 2 + 4 * 1024
+    assert bench.measured_traffic("f32", "64x2x2") == 200 * 1024 * 2 + 50 * 1024
+    assert bench.measured_traffic("f32", "16x8x2") is None
+    assert bench.measured_traffic("bf16", "64x2x2") is None
 
 
 def test_traffic_dropped_when_the_kernel_source_changes(bench, tmp_path, monkeypatch):
     with open(bench.TRAFFIC_FILE, "w") as f:
-        json.dump({"f32": {"kernel_sha": bench.kernel_sha(), "bytes_per_launch": 123}}, f)
-    assert bench.measured_traffic("f32") == 123
+        json.dump({"f32": {"kernel_sha": bench.kernel_sha(), "tiles": {"64x2x2": {"bytes_per_launch": 123}}}}, f)
+    assert bench.measured_traffic("f32", "64x2x2") == 123
     monkeypatch.setattr(bench, "kernel_sha", lambda: "0" * 16)
-    assert bench.measured_traffic("f32") is None
+    assert bench.measured_traffic("f32", "64x2x2") is None
 
 
-def test_record_traffic_rejects_an_ambiguous_run(bench, tmp_path):
+def test_record_traffic_per_tile_shape(bench, tmp_path):
+    """The autotuner runs every tile shape: each gets its own figure; a
+    shape seen by only one of the two counters gets none; a run without
+    any step kernel is an error."""
     copy = "__amd_rocclr_copyBuffer"
     _csv(tmp_path / "pc_fetch", [(copy, 1, 4.0)])
     _csv(tmp_path / "pc_write", [(copy, 1, 4.0)])
     a = "void lbm::(anonymous namespace)::k_step<0, 64, 2, 2>(lbm::StepArgs)"
     b = "void lbm::(anonymous namespace)::k_step<0, 32, 2, 4>(lbm::StepArgs)"
-    _csv(tmp_path / "pb_fetch_f32", [(a, 1, 1.0), (b, 2, 1.0)])
-    _csv(tmp_path / "pb_write_f32", [(a, 1, 1.0)])
+    c = "void lbm::(anonymous namespace)::k_step<0, 16, 8, 2>(lbm::StepArgs)"
+    _csv(tmp_path / "pb_fetch_f32", [(a, 1, 1.0), (b, 2, 2.0), (c, 3, 3.0)])
+    _csv(tmp_path / "pb_write_f32", [(a, 1, 1.0), (b, 2, 1.0)])
+    _csv(tmp_path / "pb_fetch_f16", [])
+    _csv(tmp_path / "pb_write_f16", [])
     with pytest.raises(SystemExit):
         bench.record_traffic(str(tmp_path))
+    f16 = "void lbm::(anonymous namespace)::k_step<1, 64, 2, 2>(lbm::StepArgs)"
+    _csv(tmp_path / "pb_fetch_f16", [(f16, 1, 1.0)])
+    _csv(tmp_path / "pb_write_f16", [(f16, 1, 1.0)])
+    bench.record_traffic(str(tmp_path))
+    rec = json.load(open(bench.TRAFFIC_FILE))
+    assert sorted(rec["f32"]["tiles"]) == ["32x2x4", "64x2x2"]
+    assert rec["f32"]["tiles"]["32x2x4"]["fetch_kib_per_dispatch"] == 2.0
