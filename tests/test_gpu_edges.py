@@ -7,7 +7,9 @@ norm-relative; owner maps bit for bit).
 * overlapping spheres, a sphere overlapping a wall and spheres across the
   periodic boundary (precedence: walls, then the lower sphere index);
 * a box a few nodes wide;
-* no solids at all.
+* no solids at all;
+* random small lattices with walls and drifting, overlapping spheres;
+* the full id range with spheres that cover one node or none.
 """
 import numpy as np
 import pytest
@@ -148,5 +150,32 @@ def test_random_geometry_parity(torch_stream, seed, halfway):
     o, lat = make_pair(case, halfway=halfway, stream=torch_stream)
     np.testing.assert_array_equal(lat.get_owner(), o.owner())
     advance(o, lat, case, 0, 15)
+    _check(o, lat)
+    lat.close()
+
+
+def test_id_range_full_with_tiny_spheres(torch_stream):
+    """As many bodies as the owner codes can name (3 walls and 32763 spheres:
+    the last sphere id is the largest the library accepts), most of them so
+    small that they cover one node or none, overlapping, drifting; the
+    owner map, populations and every body's force against the oracle."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    nx, ny, nz = 64, 64, 48
+    w = np.zeros((nz, ny, nx), np.uint8)
+    w[:, :, 0] = 1
+    w[10:12, 20:40, 20:44] = 2
+    w[30, :, :] = 3
+    nb = 32763
+    X = rng.uniform(0, 1, (nb, 3)) * [nx, ny, nz]
+    case = W.Case(name="tiny_many", nx=nx, ny=ny, nz=nz, tau0=0.7, smag_c=0.12, body_force=(1e-6, 0.0, 0.0),
+                  wall_id=w, wall_vel=np.array([[0.0, 0.01, 0.0], [0.0, 0.0, 0.0], [0.005, 0.0, 0.0]]),
+                  wall_ref=np.array([[0.0, 32.0, 24.0], [32.0, 30.0, 10.5], [32.0, 32.0, 30.0]]),
+                  X=X, V=rng.normal(0.0, 0.02, (nb, 3)), Omega=rng.normal(0.0, 0.01, (nb, 3)),
+                  R=rng.uniform(0.3, 1.3, nb), u_init=rng.normal(0.0, 0.01, (3, nz, ny, nx)), drift=True)
+    o, lat = make_pair(case, stream=torch_stream, max_bodies=nb)
+    own = o.owner()
+    covering = np.unique(own[own >= 3])
+    assert own.max() > 32700 and len(covering) < nb   # ids near the top; some spheres cover no node
+    advance(o, lat, case, 0, 4)
     _check(o, lat)
     lat.close()
