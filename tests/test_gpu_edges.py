@@ -9,7 +9,8 @@ norm-relative; owner maps bit for bit).
 * a box a few nodes wide;
 * no solids at all;
 * random small lattices with walls and drifting, overlapping spheres;
-* the full id range with spheres that cover one node or none.
+* the full id range with spheres that cover one node or none;
+* a sphere at the radius limit, next to its own periodic image.
 """
 import numpy as np
 import pytest
@@ -179,3 +180,22 @@ def test_id_range_full_with_tiny_spheres(torch_stream):
     advance(o, lat, case, 0, 4)
     _check(o, lat)
     lat.close()
+
+
+def test_sphere_at_the_radius_limit(torch_stream):
+    """A sphere just below the largest radius the library accepts (half the
+    smallest box side minus one): its box nearly spans the periodic lattice
+    and it nearly touches its own periodic image, with a small sphere in the
+    gap; drifting and spinning, both link modes."""
+    rng = np.random.Generator(np.random.PCG64(31))
+    nx, ny, nz = 24, 26, 28
+    for halfway in (False, True):
+        case = W.Case(name="radius_limit", nx=nx, ny=ny, nz=nz, tau0=0.65, smag_c=0.1, body_force=(1e-6, 0.0, 0.0),
+                      X=np.array([[11.3, 12.6, 13.9], [23.4, 12.2, 13.1]]), V=np.array([[0.02, -0.01, 0.01], [0.0, 0.01, 0.0]]),
+                      Omega=np.array([[0.002, 0.001, -0.003], [0.0, 0.0, 0.01]]), R=np.array([10.95, 0.9]),
+                      u_init=rng.normal(0.0, 0.01, (3, nz, ny, nx)), drift=True)
+        o, lat = make_pair(case, halfway=halfway, stream=torch_stream)
+        np.testing.assert_array_equal(lat.get_owner(), o.owner())
+        advance(o, lat, case, 0, 12)
+        _check(o, lat)
+        lat.close()
