@@ -270,6 +270,7 @@ def main():
         "mflups": main_run["mflups"],
         "ms_per_step_median5": main_run["ms_per_step_median5"],
         "ms_per_step_host_forces": main_run["ms_per_step_host_forces"],
+        "ms_per_step_host_io": main_run["ms_per_step_host_io"],
         "roofline": main_run["roofline"],
     }
     if args.mixed and args.storage == "f32" and not args.static:
@@ -396,7 +397,7 @@ def timed_run(case, storage, K, Wm):
     tabs = None
     K2 = min(K, 50)
     nr = max(K // 5, 1)
-    nt = Wm + K + 5 * nr + K2
+    nt = Wm + K + 5 * nr + 2 * K2
     if case.drift:
         tabs = torch.empty((nt, nb, 10), dtype=torch.float64, device="cuda")
         for n in range(1, nt + 1):
@@ -451,6 +452,19 @@ def timed_run(case, storage, K, Wm):
         lat.step(1)
         lat.get_forces()
     dt_host = time.perf_counter() - t0
+    # K2 more steps as a host-side DEM would couple: the bodies' host arrays
+    # handed over (copied to the device by the library), the step, the
+    # forces copied back to the host
+    first = Wm + K + 5 * nr + K2 + 1
+    host_tabs = [case.bodies_at(n) for n in range(first, first + K2)] if case.drift else []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(K2):
+        if host_tabs:
+            lat.set_bodies(*host_tabs[n])
+        lat.step(1)
+        lat.get_forces()
+    dt_host_io = time.perf_counter() - t0
     lat.close()
 
     N = case.n_nodes
@@ -473,6 +487,7 @@ def timed_run(case, storage, K, Wm):
     return {"value": round(N * K / dt / 1e6, 1), "ms_per_step": round(dt / K * 1e3, 4),
             "ms_per_step_median5": round(float(np.median(reps)) * 1e3, 4),
             "ms_per_step_host_forces": round(dt_host / K2 * 1e3, 4),
+            "ms_per_step_host_io": round(dt_host_io / K2 * 1e3, 4),
             "mflups": round(nf * K / dt / 1e6, 1), "fluid_nodes": int(nf), "roofline": roof}
 
 
