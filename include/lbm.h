@@ -203,7 +203,10 @@ lbm_status lbm_get_owner(lbm_handle h, int32_t *owner);
  * the populations (storage type), owner map, body and wall tables and
  * counters are written to buf (host, *bytes >= size).  lbm_set_state
  * restores a checkpoint of a handle with the same configuration; resuming
- * reproduces the populations bit for bit.  Errors: ARG, STATE, HIP. */
+ * reproduces the populations bit for bit.  It checks the buffer on the host
+ * before copying anything: size, configuration, body and wall counts within
+ * the handle's capacities and wall ids within the wall count; a rejected
+ * buffer leaves the handle as it was.  Errors: ARG, STATE, HIP. */
 lbm_status lbm_get_state(lbm_handle h, void *buf, size_t *bytes);
 lbm_status lbm_set_state(lbm_handle h, const void *buf, size_t bytes);
 

@@ -871,6 +871,16 @@ lbm_status lbm_set_state(lbm_handle h, const void *buf, size_t bytes)
     if (memcmp(hd.magic, "LBMSTAT1", 8) != 0 || hd.nx != h->cfg.nx || hd.ny != h->cfg.ny || hd.nz != h->cfg.nz ||
         hd.storage != h->cfg.storage || hd.max_bodies != h->cfg.max_bodies || hd.max_walls != h->cfg.max_walls)
         return fail(h, LBM_ERR_ARG, "state does not match this handle's configuration");
+    if (hd.nb_state < 0 || hd.nb_state > h->cfg.max_bodies || hd.nb_next < 0 || hd.nb_next > h->cfg.max_bodies ||
+        hd.n_walls < 0 || hd.n_walls > h->cfg.max_walls || (hd.dirty != 0 && hd.dirty != 1) || hd.steps_done < 0)
+        return fail(h, LBM_ERR_ARG, "state header out of range (bodies %d/%d, walls %d, dirty %d, steps %d)",
+                    hd.nb_state, hd.nb_next, hd.n_walls, hd.dirty, hd.steps_done);
+    {
+        // wall ids of the voxel map within the state's wall count
+        const uint8_t *wm = reinterpret_cast<const uint8_t *>(buf) + sizeof hd + popb + sizeof(uint16_t) * h->N;
+        for (int n = 0; n < h->N; ++n)
+            if (wm[n] > hd.n_walls) return fail(h, LBM_ERR_ARG, "state wall map names wall %d of %d", wm[n], hd.n_walls);
+    }
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     const char *p = static_cast<const char *>(buf) + sizeof hd;
     TRY(copy_sync(h, h->pop[h->cur], p, popb, hipMemcpyHostToDevice));

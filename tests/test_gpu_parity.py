@@ -251,6 +251,35 @@ def test_state_checkpoint_resume_bitwise(torch_stream):
     lat2.close()
 
 
+def test_state_rejects_a_corrupt_header(torch_stream):
+    """Checkpoint headers with body or wall counts beyond the handle's
+    capacities, or a bad flag, are rejected on the host; the handle then
+    steps on exactly as if nothing had been offered."""
+    import struct
+    from paper_1703_05158_amd import LBMError, Lattice
+    case = W.case_box(n=(20, 18, 16), n_spheres=3, radius=(2.0, 3.0), v_sigma=0.02, seed=9, drift=True)
+    lat = Lattice.from_case(case, stream=torch_stream, max_bodies=4)
+    ref = Lattice.from_case(case, stream=torch_stream, max_bodies=4)
+    for l in (lat, ref):
+        l.set_bodies(*case.bodies_at(1))
+        l.step(1)
+    good = bytearray(lat.get_state())
+    # header: 8-byte tag, then int32 version, nx, ny, nz, storage, n_walls,
+    # nb_state, nb_next, dirty, steps_done, max_bodies, max_walls
+    for off, val in ((32, 5), (36, -1), (28, 1), (40, 2), (44, -3)):
+        bad = bytearray(good)
+        struct.pack_into("<i", bad, off, val)
+        with pytest.raises(LBMError):
+            lat.set_state(bytes(bad))
+    for n in range(2, 5):
+        for l in (lat, ref):
+            l.set_bodies(*case.bodies_at(n))
+            l.step(1)
+    np.testing.assert_array_equal(lat.get_populations(), ref.get_populations())
+    lat.close()
+    ref.close()
+
+
 def test_nan_guard_reports_unstable(torch_stream):
     from paper_1703_05158_amd import LBMError, Lattice
     case = W.case_box(n=(16, 16, 16), n_spheres=0, u_sigma=0.0, seed=0)
