@@ -292,10 +292,10 @@ lbm_status lbm_autotune_tile(lbm_handle h, int32_t trial_steps, const char *cach
 
 /* Batched stepping of independent lattices (a parameter sweep of many
  * boxes): every step of the batch is one replay of a captured hipGraph that
- * runs the link pass of all members as one persistent launch over their
- * spheres and wall-link chunks, the wall totals, the step kernel of all
- * members as one persistent launch over their tiles (each member with its
- * own parameters), and a parity flip.  Each member's results
+ * runs the link pass of all members as one launch over their spheres and
+ * wall-link chunks, the wall totals, the step kernel of all members as one
+ * persistent launch over their tiles (each member with its own
+ * parameters), and a parity flip.  Each member's results
  * are bit for bit those of lbm_step on that member.
  *   members : n distinct handles, all past lbm_init_fields, same storage,
  *             no bodies set since their last step (their own tile shapes

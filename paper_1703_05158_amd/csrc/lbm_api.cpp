@@ -1207,7 +1207,7 @@ struct lbm_batch_ctx {
     BatchStepArgs bs{};
     BatchLinkArgs bl{};
     int shape = kTile64x2x2;       // tile shape of the batched step kernel
-    int grid_step = 0, grid_links = 0;
+    int grid_step = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::string err;
@@ -1238,7 +1238,7 @@ lbm_status bfail(lbm_batch_ctx *b, lbm_status st, const char *fmt, ...)
 // persistent step kernel over every member's tiles, and the parity flip.
 lbm_status batch_enqueue(lbm_batch_ctx *b)
 {
-    BHIP_TRY(b, launch_batch_links(b->storage, b->bl, b->grid_links, b->stream));
+    BHIP_TRY(b, launch_batch_links(b->storage, b->bl, b->stream));
     BHIP_TRY(b, launch_batch_wall_forces(b->bl, b->stream));
     BHIP_TRY(b, launch_batch_step(b->storage, b->shape, b->bs, b->grid_step, b->stream));
     BHIP_TRY(b, launch_batch_flip(b->d_cur, (int)b->m.size(), b->stream));
@@ -1256,8 +1256,8 @@ void batch_release(lbm_batch_ctx *b)
     b->d_members = nullptr;
 }
 
-// Member tables for the batch's tile shape, persistent grid sizes, and the
-// captured graph of one step.
+// Member tables for the batch's tile shape, the step kernel's persistent
+// grid size, and the captured graph of one step.
 lbm_status batch_build(lbm_batch_ctx *b)
 {
     batch_release(b);
@@ -1296,11 +1296,10 @@ lbm_status batch_build(lbm_batch_ctx *b)
     int dev = 0, cus = 0;
     BHIP_TRY(b, hipGetDevice(&dev));
     BHIP_TRY(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    // persistent grids: as many workgroups as are resident at once (a
-    // whole number per XCD for the step kernel)
-    const int rs = batch_step_blocks_per_cu(b->storage, b->shape), rl = batch_links_blocks_per_cu(b->storage);
+    // the persistent step kernel: as many workgroups as are resident at once,
+    // a whole number per XCD (the link kernel takes one workgroup per item)
+    const int rs = batch_step_blocks_per_cu(b->storage, b->shape);
     b->grid_step = std::max(8, std::min(cus * rs / 8 * 8, (tiles + 7) / 8 * 8));
-    b->grid_links = std::max(1, std::min(cus * rl, items));
     // capture one step in a graph, replayed once per step
     BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     const lbm_status st = batch_enqueue(b);

@@ -97,7 +97,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks)
 
 // A copy of v that the compiler knows to be the same in every lane (the
 // value of the first active lane), so that it can live in scalar registers:
-// for argument blocks that a persistent kernel loads from memory.
+// for argument blocks that a kernel loads from memory (the batch kernels).
 template <typename T>
 __device__ __forceinline__ T uniform(const T &v)
 {

@@ -153,9 +153,8 @@ struct GeomArgs {
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t s);
 hipError_t launch_links(int storage, const LinkArgs &a, hipStream_t s);
 hipError_t launch_batch_step(int storage, int shape, const BatchStepArgs &b, int grid, hipStream_t s);
-int batch_step_blocks_per_cu(int storage, int shape);   // resident workgroups per CU of the persistent kernels
-int batch_links_blocks_per_cu(int storage);
-hipError_t launch_batch_links(int storage, const BatchLinkArgs &b, int grid, hipStream_t s);
+int batch_step_blocks_per_cu(int storage, int shape);   // resident workgroups per CU of the persistent step kernel
+hipError_t launch_batch_links(int storage, const BatchLinkArgs &b, hipStream_t s);
 hipError_t launch_batch_wall_forces(const BatchLinkArgs &b, hipStream_t s);
 hipError_t launch_batch_flip(int *cur, int n, hipStream_t s);
 

@@ -652,32 +652,26 @@ __device__ __forceinline__ int find_member(int n, int g, F key)
     return m;
 }
 
-// Persistent link pass over many lattices: item j of member m is sphere j
-// (j < nb) or wall chunk j - nb.
+// Link pass over many lattices: one workgroup per item, item j of member m
+// being sphere j (j < nb, taken in the member's sphere order) or wall chunk
+// j - nb.  Not persistent: without a loop over items the kernel fits 168
+// VGPRs, i.e. 3 waves per SIMD.
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_batch_links(BatchLinkArgs b)
+__global__ __launch_bounds__(kBlock, 3) void k_batch_links(BatchLinkArgs b)
 {
     __shared__ SphereLds L;
     __shared__ double s_red[kWaves][6];
-    int mb = 0, me = 0;
-    LinkArgs a{};
-    for (int g = blockIdx.x; g < b.total_items; g += gridDim.x) {
-        if (g < mb || g >= me) {  // the member of the previous item is kept
-            const int m = find_member(b.n, g, [&](int i) { return b.members[i].item_begin; });
-            const BatchMember &bm = b.members[m];
-            mb = bm.item_begin;
-            me = m + 1 < b.n ? b.members[m + 1].item_begin : b.total_items;
-            LinkArgs t = bm.links;
-            t.pop = bm.pop[b.cur[m]];
-            a = uniform(t);
-        }
-        const int j = g - mb;
-        if (j < a.nb)
-            sphere_block<S>(a, j, L, s_red);
-        else
-            wall_block<S>(a, j - a.nb, s_red);
-        __syncthreads();  // LDS is reused by the next item
-    }
+    const int g = blockIdx.x;
+    const int m = find_member(b.n, g, [&](int i) { return b.members[i].item_begin; });
+    const BatchMember &bm = b.members[m];
+    LinkArgs t = bm.links;
+    t.pop = bm.pop[b.cur[m]];
+    const LinkArgs a = uniform(t);
+    const int j = g - bm.item_begin;
+    if (j < a.nb)
+        sphere_block<S>(a, a.order ? a.order[j] : j, L, s_red);
+    else
+        wall_block<S>(a, j - a.nb, s_red);
 }
 
 // Wall totals of every member: one 64-thread workgroup per wall.
@@ -706,21 +700,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_flip(int *cur, int n)
 
 }  // namespace
 
-int batch_links_blocks_per_cu(int storage)
-{
-    int n = 0;
-    hipError_t e = hipErrorInvalidValue;
-    switch (storage) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_links<0>, kBlock, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_links<1>, kBlock, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_links<2>, kBlock, 0); break;
-    }
-    return e == hipSuccess && n > 0 ? n : 1;
-}
-
-hipError_t launch_batch_links(int storage, const BatchLinkArgs &b, int grid, hipStream_t s)
+hipError_t launch_batch_links(int storage, const BatchLinkArgs &b, hipStream_t s)
 {
     if (b.total_items <= 0) return hipSuccess;
+    const int grid = b.total_items;
     switch (storage) {
     case 0: hipLaunchKernelGGL(k_batch_links<0>, dim3(grid), dim3(kBlock), 0, s, b); break;
     case 1: hipLaunchKernelGGL(k_batch_links<1>, dim3(grid), dim3(kBlock), 0, s, b); break;
