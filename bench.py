@@ -218,6 +218,8 @@ def main():
     ap.add_argument("--no-sweep", dest="sweep", action="store_false",
                     help="skip the batched 48-instance parameter sweep")
     ap.add_argument("--sweep-steps", type=int, default=500)
+    ap.add_argument("--no-zieb", dest="zieb", action="store_false",
+                    help="skip the run with the inflow plane")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
                     help="skip the drag-gradient run")
     ap.add_argument("--cpu-steps", type=int, default=15, help="oracle sample steps (0: skip)")
@@ -289,6 +291,8 @@ def main():
         out["mixed_precision"] = mixed
     if args.sweep and args.storage == "f32" and not args.static:
         out["batched_sweep"] = sweep_run(args.sweep_steps)
+    if args.zieb and args.storage == "f32" and not args.static:
+        out["zieb"] = zieb_run(main_run["ms_per_step"])
     if args.adjoint and args.storage == "f32" and not args.static:
         out["adjoint"] = adjoint_run()
     if args.cpu_steps > 0 and not args.static:
@@ -297,6 +301,59 @@ def main():
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps, args.cpu_threads)
         out["cpu_baseline"]["gpu_over_oracle"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
     print(json.dumps(out), flush=True)
+
+
+def zieb_run(plain_ms, steps=100, warmup=10):
+    """The duct with the paper's inflow plane (Sec. 2.6) in place of the
+    piston: the piston layer z = 0 held still, the plane z = 1 fed by a
+    virtual cylinder of the duct's cross-section moving at the piston's
+    speed, the spheres drifting as in the main run.  Per step as the main
+    run: the bodies' device table, the step, the forces into a device
+    history."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import lbm_workloads as W
+    from paper_1703_05158_amd import Lattice
+
+    base = W.case_piston_duct(drift=True)
+    v_piston = float(base.wall_vel[1][2])
+    wv = base.wall_vel.copy()
+    wv[1] = 0.0
+    case = dataclasses.replace(base, wall_vel=wv)
+    area = float((case.wall_id[1] == 0).sum())
+    volume = area * case.nz / 2
+    stream = torch.cuda.current_stream()
+    lat = Lattice.from_case(case, stream=stream.cuda_stream, init=False)
+    lat.set_zieb(1, area, volume, v_piston)
+    lat.init_fields(case.rho_init, case.u_init)
+    nb, nbt = case.n_bodies, case.n_bodies + case.n_walls
+    tabs = torch.empty((warmup + steps, nb, 10), dtype=torch.float64, device="cuda")
+    for n in range(1, warmup + steps + 1):
+        X, V, Om, R = case.bodies_at(n)
+        tabs[n - 1] = torch.from_numpy(np.concatenate([X, V, Om, R[:, None]], 1))
+    hist = torch.zeros((steps, nbt, 6), dtype=torch.float64, device="cuda")
+    for n in range(warmup):
+        lat.set_bodies_device(nb, tabs[n])
+        lat.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(steps):
+        lat.set_bodies_device(nb, tabs[warmup + n])
+        lat.step(1)
+        lat.get_forces_device(hist[n])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rho, H, vf = lat.zieb_state()
+    lat.close()
+    assert torch.isfinite(hist).all().item()
+    ms = dt / steps * 1e3
+    return {"workload": "piston_duct_128x128x512_4000spheres_drift_inflow_plane", "plane_z": 1,
+            "area": area, "volume": volume, "v_piston": v_piston, "steps": steps,
+            "ms_per_step": round(ms, 4), "value": round(case.n_nodes / ms / 1e3, 1), "unit": "MLUPS",
+            "over_piston_duct": round(ms / plain_ms, 3), "rho_cylinder": rho, "piston_travel": H}
 
 
 def adjoint_run(steps=200, ckpt=20):

@@ -54,6 +54,7 @@ struct lbm_ctx {
     int zieb_z = -1;
     double zieb_area = 0.0, zieb_volume = 0.0, zieb_vp = 0.0;
     double *zstate = nullptr;          // ZiebState on the device
+    double *zpart = nullptr;           // kZiebMaxBlocks * 3 doubles, then a uint32 counter: the plane reduction
     int *flag = nullptr;
     int *flag_host = nullptr;
     double *scratch = nullptr;         // 4N doubles, export/import staging (lazy)
@@ -183,6 +184,8 @@ ZiebArgs zieb_args(const lbm_ctx *h)
     z.own = h->own;
     z.pop = h->pop[h->cur];
     z.state = h->zstate;
+    z.part = h->zpart;
+    z.done = reinterpret_cast<unsigned int *>(h->zpart + 3 * kZiebMaxBlocks);
     return z;
 }
 
@@ -453,6 +456,7 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         dalloc(h, &h->acc, sizeof(double) * 6 * std::max(nbt, 1)) != hipSuccess ||
         dalloc(h, &h->order, sizeof(int) * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->zstate, sizeof(ZiebState)) != hipSuccess ||
+        dalloc(h, &h->zpart, sizeof(double) * (3 * kZiebMaxBlocks + 1)) != hipSuccess ||
         dalloc(h, &h->flag, sizeof(int)) != hipSuccess)
         return bail(LBM_ERR_OOM);
     if (hipHostMalloc((void **)&h->pinned, sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
@@ -464,7 +468,8 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         hipMemsetAsync(h->pop[0], 0, popb, h->stream) != hipSuccess ||
         hipMemsetAsync(h->pop[1], 0, popb, h->stream) != hipSuccess ||
         hipMemsetAsync(h->acc, 0, sizeof(double) * 6 * std::max(nbt, 1), h->stream) != hipSuccess ||
-        hipMemsetAsync(h->flag, 0, sizeof(int), h->stream) != hipSuccess)
+        hipMemsetAsync(h->flag, 0, sizeof(int), h->stream) != hipSuccess ||
+        hipMemsetAsync(h->zpart + 3 * kZiebMaxBlocks, 0, sizeof(double), h->stream) != hipSuccess)
         return bail(LBM_ERR_HIP);
     if (rasterize_full(h) != LBM_OK) return bail(LBM_ERR_HIP);
     if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(LBM_ERR_HIP);
@@ -482,7 +487,7 @@ void lbm_destroy(lbm_handle h)
     }
     free_wall_links(h);
     void *dev[] = {h->pop[0], h->pop[1], h->own, h->wall_map, h->tab[0], h->tab[1],
-                   h->walls, h->acc, h->order, h->flag, h->scratch, h->zstate};
+                   h->walls, h->acc, h->order, h->flag, h->scratch, h->zstate, h->zpart};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (h->pinned) (void)hipHostFree(h->pinned);

@@ -61,6 +61,8 @@ struct ZiebState {
     double pad;
 };
 
+constexpr int kZiebMaxBlocks = 1024;  // workgroups of the plane reduction (a grid-stride loop beyond)
+
 struct ZiebArgs {
     int nx, ny, nz, N, Ns, z;
     float rho0, fz;
@@ -68,6 +70,8 @@ struct ZiebArgs {
     const uint16_t *own;
     const void *pop;              // current state
     double *state;                // ZiebState
+    double *part;                 // [kZiebMaxBlocks][3]: per-workgroup sums
+    unsigned int *done;           // workgroups finished (0 between updates)
 };
 
 // Boundary-link pass: for every link from a fluid node x to a solid node

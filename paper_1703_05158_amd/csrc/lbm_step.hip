@@ -249,20 +249,23 @@ hipError_t launch_step_s(const StepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-// The virtual cylinder's update of one step (one workgroup): the mean
-// in-flowing velocity v_f and density of the plane's fluid nodes from the
-// current state (u = (sum f c - F/2)/rho), then eq. (ZIEBdesity8) for the
-// cylinder density, which the plane takes in this step, and the piston
-// displacement.  Sums in FP64 in a fixed order.
+// The virtual cylinder's update of one step: the mean in-flowing velocity
+// v_f and density of the plane's fluid nodes from the current state
+// (u = (sum f c - F/2)/rho), then eq. (ZIEBdesity8) for the cylinder
+// density, which the plane takes in this step, and the piston displacement.
+// Each workgroup sums a run of the plane in FP64; the last one to finish
+// adds the workgroups' sums in workgroup order (so the result does not
+// depend on the launch's timing), updates the state and clears the counter.
 template <int S>
-__global__ __launch_bounds__(1024) void k_zieb_update(ZiebArgs z)
+__global__ __launch_bounds__(kBlock) void k_zieb_update(ZiebArgs z)
 {
     using St = Store<S>;
     const typename St::T *pop = static_cast<const typename St::T *>(z.pop);
-    __shared__ double s_red[3][16];
+    constexpr int kW = kBlock / 64;
+    __shared__ double s_red[3][kW];
     double su = 0.0, sr = 0.0, sc = 0.0;
     const int plane = z.nx * z.ny;
-    for (int k = threadIdx.x; k < plane; k += blockDim.x) {
+    for (int k = blockIdx.x * kBlock + threadIdx.x; k < plane; k += gridDim.x * kBlock) {
         const uint32_t n = (uint32_t)(k + plane * z.z);
         if (z.own[n] < kVacated) continue;
         double rd = 0.0, jz = 0.0;
@@ -288,20 +291,33 @@ __global__ __launch_bounds__(1024) void k_zieb_update(ZiebArgs z)
         s_red[2][wv] = sc;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double tu = 0.0, tr = 0.0, tc = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-            tu += s_red[0][w];
-            tr += s_red[1][w];
-            tc += s_red[2][w];
-        }
-        const double vf = tc > 0.0 ? tu / tc : 0.0;
-        double *st = z.state;
-        const double rho = st[0] < 0.0 ? (tc > 0.0 ? tr / tc : (double)z.rho0) : st[0];
-        st[0] = rho * exp((z.vp * z.area - vf * z.area) / (z.volume - z.area * st[1]));
-        st[1] += z.vp;
-        st[2] = vf;
+    if (threadIdx.x != 0) return;
+    double bu = 0.0, br = 0.0, bc = 0.0;
+    for (int w = 0; w < kW; ++w) {
+        bu += s_red[0][w];
+        br += s_red[1][w];
+        bc += s_red[2][w];
     }
+    double *pp = z.part + 3 * (size_t)blockIdx.x;
+    __hip_atomic_store(pp, bu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(pp + 1, br, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(pp + 2, bc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the sums are visible before the count that announces them
+    if (__hip_atomic_fetch_add(z.done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) != gridDim.x - 1) return;
+    double tu = 0.0, tr = 0.0, tc = 0.0;
+    for (int b = 0; b < (int)gridDim.x; ++b) {
+        const double *q = z.part + 3 * (size_t)b;
+        tu += __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        tr += __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        tc += __hip_atomic_load(q + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const double vf = tc > 0.0 ? tu / tc : 0.0;
+    double *st = z.state;
+    const double rho = st[0] < 0.0 ? (tc > 0.0 ? tr / tc : (double)z.rho0) : st[0];
+    st[0] = rho * exp((z.vp * z.area - vf * z.area) / (z.volume - z.area * st[1]));
+    st[1] += z.vp;
+    st[2] = vf;
+    __hip_atomic_store(z.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---- reverse mode (gradient of the summed sphere drag) ------------------
@@ -576,10 +592,11 @@ hipError_t launch_adj_reduce(const double *dF_tile, int n_tiles, double *dF, hip
 
 hipError_t launch_zieb_update(int storage, const ZiebArgs &z, hipStream_t s)
 {
+    const int grid = std::min(kZiebMaxBlocks, std::max(1, (z.nx * z.ny + kBlock - 1) / kBlock));
     switch (storage) {
-    case 0: hipLaunchKernelGGL(k_zieb_update<0>, dim3(1), dim3(1024), 0, s, z); break;
-    case 1: hipLaunchKernelGGL(k_zieb_update<1>, dim3(1), dim3(1024), 0, s, z); break;
-    case 2: hipLaunchKernelGGL(k_zieb_update<2>, dim3(1), dim3(1024), 0, s, z); break;
+    case 0: hipLaunchKernelGGL(k_zieb_update<0>, dim3(grid), dim3(kBlock), 0, s, z); break;
+    case 1: hipLaunchKernelGGL(k_zieb_update<1>, dim3(grid), dim3(kBlock), 0, s, z); break;
+    case 2: hipLaunchKernelGGL(k_zieb_update<2>, dim3(grid), dim3(kBlock), 0, s, z); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
