@@ -132,3 +132,40 @@ def test_zieb_with_spheres_crossing_the_plane(torch_stream):
     assert pe <= 1e-5 and fe <= 1e-4 and te <= 1e-4
     assert rho == pytest.approx(o.zieb["rho"], rel=1e-6)
     lat.close()
+
+
+def test_zieb_plane_wider_than_the_reduction_grid(torch_stream):
+    """A plane of 520 x 520 nodes: more than the plane reduction's largest
+    grid covers at one node per thread (1024 workgroups of 256), so its
+    workgroups loop over the plane; the cylinder state and the populations
+    against the oracle."""
+    import oracle
+    from paper_1703_05158_amd import Lattice
+    nx, ny, nz = 520, 520, 5
+    assert nx * ny > 1024 * 256
+    w = np.zeros((nz, ny, nx), np.uint8)
+    w[0] = 1            # the removed domain below the plane z = 1
+    w[nz - 1] = 1       # closed far end
+    w[:, 0, :] = 1
+    rng = np.random.Generator(np.random.PCG64(41))
+    case = W.Case(name="zieb_wide", nx=nx, ny=ny, nz=nz, tau0=0.8, smag_c=0.1, wall_id=w,
+                  wall_vel=np.zeros((1, 3)), wall_ref=np.zeros((1, 3)),
+                  X=np.array([[100.5, 200.2, 2.4]]), V=np.zeros((1, 3)), Omega=np.zeros((1, 3)), R=np.array([1.4]),
+                  u_init=rng.normal(0.0, 0.005, size=(3, nz, ny, nx)))
+    zp = (1, float((w[1] == 0).sum()), 2.0 * float((w == 0).sum()), 0.01)
+    o = oracle.Oracle.from_case(case, init=False)
+    o.set_zieb(*zp)
+    o.init_fields(case.rho_init, case.u_init)
+    lat = Lattice.from_case(case, stream=torch_stream, init=False)
+    lat.set_zieb(*zp)
+    lat.init_fields(case.rho_init, case.u_init)
+    for n in range(2):
+        o.step(1)
+        lat.step(1)
+    rho, H, vf = lat.zieb_state()
+    pe = pop_rel_err(o, lat)
+    print(f"pop {pe:.2e} rho {rho:.10f} (oracle {o.zieb['rho']:.10f}) vf {vf:.3e} ({o.zieb['vf']:.3e})")
+    assert pe <= 1e-5
+    assert rho == pytest.approx(o.zieb["rho"], rel=1e-6)
+    assert vf == pytest.approx(o.zieb["vf"], abs=1e-7)
+    lat.close()
