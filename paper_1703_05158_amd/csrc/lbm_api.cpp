@@ -59,6 +59,7 @@ struct lbm_ctx {
     int *flag_host = nullptr;
     double *scratch = nullptr;         // 4N doubles, export/import staging (lazy)
     double *pinned = nullptr;          // max_bodies * 10 doubles, set_bodies staging
+    double *forces_pin = nullptr;      // (max_bodies + max_walls) * 6 doubles, get_forces staging
     int *order = nullptr;              // max_bodies: sphere order of the link pass (Morton order of the centres)
     int *order_pin = nullptr;          // its host staging
     int n_order = 0;                   // body count the order was made for (0: none)
@@ -460,6 +461,7 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         dalloc(h, &h->flag, sizeof(int)) != hipSuccess)
         return bail(LBM_ERR_OOM);
     if (hipHostMalloc((void **)&h->pinned, sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
+        hipHostMalloc((void **)&h->forces_pin, sizeof(double) * 6 * std::max(nbt, 1)) != hipSuccess ||
         hipHostMalloc((void **)&h->order_pin, sizeof(int) * std::max(c.max_bodies, 1)) != hipSuccess ||
         hipHostMalloc((void **)&h->flag_host, sizeof(int)) != hipSuccess)
         return bail(LBM_ERR_OOM);
@@ -491,6 +493,7 @@ void lbm_destroy(lbm_handle h)
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (h->pinned) (void)hipHostFree(h->pinned);
+    if (h->forces_pin) (void)hipHostFree(h->forces_pin);
     if (h->order_pin) (void)hipHostFree(h->order_pin);
     if (h->flag_host) (void)hipHostFree(h->flag_host);
     if (h->stage_evt) (void)hipEventDestroy(h->stage_evt);
@@ -720,8 +723,9 @@ lbm_status lbm_get_forces(lbm_handle h, double *F, double *T)
     if (st != LBM_OK) return st;
     const int nbt = h->nb_state + h->n_walls;
     if (nbt > 0 && (!F || !T)) return fail(h, LBM_ERR_ARG, "NULL output");
-    std::vector<double> buf((size_t)6 * std::max(nbt, 1));
-    HIP_TRY(h, hipMemcpyAsync(buf.data(), h->acc, sizeof(double) * 6 * nbt, hipMemcpyDeviceToHost, h->stream));
+    // through the pinned staging buffer: one DMA, no per-call allocation
+    const double *buf = h->forces_pin;
+    HIP_TRY(h, hipMemcpyAsync(h->forces_pin, h->acc, sizeof(double) * 6 * nbt, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     for (int b = 0; b < nbt; ++b)
         for (int a = 0; a < 3; ++a) {
