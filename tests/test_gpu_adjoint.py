@@ -109,3 +109,43 @@ def test_drag_gradient_rejects_unsupported(torch_stream):
     with pytest.raises(LBMError):
         lat.drag_gradient(4, 2)   # walls
     lat.close()
+
+
+def test_gradient_on_a_32cube_subset_of_the_adjoint_workload(torch_stream):
+    """The 96x96x192 drag-gradient workload cut to a 32^3 subset (about its
+    sphere density: 5 spheres of radius 4; body force 5e-6 along x, tau0
+    0.6, C 0.1): the GPU gradient against the FP64 reverse-mode reference,
+    and dJ/dV against central differences with h = 1e-4 of J run forward
+    on the GPU (J is linear in V, so the difference is exact up to the FP32
+    rounding of J)."""
+    import oracle
+    from oracle.adjoint import DragProblem
+    from paper_1703_05158_amd import Lattice
+    base = W.case_box(n=(32, 32, 32), n_spheres=5, radius=(4.0, 4.0), tau0=0.6, smag_c=0.1,
+                      body_force=(5e-6, 0.0, 0.0), u_sigma=0.0, gap=2.0, seed=21)
+    rng = np.random.Generator(np.random.PCG64(121))
+    case = dataclasses.replace(base, V=rng.normal(0.0, 0.01, size=(5, 3)))
+    steps, ckpt = 40, 10
+    o = oracle.Oracle.from_case(case)
+    Jr, gFr, gVr = DragProblem(o).gradient(o.populations(), case.body_force, case.V, steps)
+    lat = Lattice.from_case(case, stream=torch_stream)
+    J, gF, gV = lat.drag_gradient(steps, ckpt)
+    lat.close()
+    print(f"J {J:.9e} ({Jr:.9e})  dF err {_rel(gF, gFr):.2e}  dV err {_rel(gV, gVr):.2e}")
+    assert J == pytest.approx(Jr, rel=1e-5)
+    assert _rel(gF, gFr) < 1e-3 and _rel(gV, gVr) < 1e-3
+
+    def J_of(V):
+        l = Lattice.from_case(dataclasses.replace(case, V=V), stream=torch_stream)
+        l.step(steps)
+        F, _ = l.get_forces()
+        l.close()
+        return float(F[:case.n_bodies, 0].sum())
+    h = 1e-4
+    for b, a in ((0, 0), (2, 1), (4, 2)):
+        Vp, Vm = case.V.copy(), case.V.copy()
+        Vp[b, a] += h
+        Vm[b, a] -= h
+        fd = (J_of(Vp) - J_of(Vm)) / (2 * h)
+        print(f"dJ/dV[{b},{a}] {gV[b, a]:.6e} fd {fd:.6e}")
+        assert gV[b, a] == pytest.approx(fd, rel=2e-3, abs=2e-3 * np.max(np.abs(gV)))
