@@ -85,3 +85,14 @@ def test_record_traffic_per_tile_shape(bench, tmp_path):
     rec = json.load(open(bench.TRAFFIC_FILE))
     assert sorted(rec["f32"]["tiles"]) == ["32x2x4", "64x2x2"]
     assert rec["f32"]["tiles"]["32x2x4"]["fetch_kib_per_dispatch"] == 2.0
+
+
+def test_more_than_one_gpu_is_refused():
+    """The bench runs on one GPU; asking for more exits with status 2 and
+    says so, before any device work."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
