@@ -330,3 +330,43 @@ def test_profile_counts_launches(torch_stream):
     assert n == 7 and ms > 0
     lat.profile(False)
     lat.close()
+
+
+def test_device_table_entries_out_of_range_are_ignored(torch_stream):
+    """A device body table is not checked on the host: a sphere whose radius
+    is outside (0, min(n)/2 - 1) or whose centre is outside the box (NaN
+    included) is ignored by the rasteriser and the link pass.  The same run
+    with those entries replaced by spheres too small to cover a node gives
+    the same owner map, populations and forces, bit for bit."""
+    import torch
+    from paper_1703_05158_amd import Lattice
+    case = W.case_box(n=(24, 22, 20), n_spheres=5, radius=(2.0, 3.0), v_sigma=0.02, seed=13, drift=False)
+    a = Lattice.from_case(case, stream=torch_stream)
+    b = Lattice.from_case(case, stream=torch_stream)
+    tab = np.concatenate([case.X, case.V, case.Omega, case.R[:, None]], 1)
+    bad, tiny = tab.copy(), tab.copy()
+    bad[1, 9] = 0.0                 # radius 0
+    bad[2, 0] = np.nan              # centre not a number
+    bad[3, 9] = 9.5                 # radius above 0.5 * 20 - 1
+    bad[4, 0] = 24.0                # centre on x = nx, outside [0, nx)
+    for i, c in ((1, 5.5), (2, 8.5), (3, 11.5), (4, 14.5)):
+        tiny[i] = [c, 10.5, 9.5, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.1]   # half-integer centre, covers no node
+    keep = []
+    for n in range(4):
+        tab[0, :3] += tab[0, 3:6]   # sphere 0 drifts in both runs
+        bad[0], tiny[0] = tab[0], tab[0]
+        tb, tt = torch.tensor(bad, device="cuda"), torch.tensor(tiny, device="cuda")
+        keep += [tb, tt]
+        a.set_bodies_device(5, tb)
+        b.set_bodies_device(5, tt)
+        a.step(1)
+        b.step(1)
+    np.testing.assert_array_equal(a.get_owner(), b.get_owner())
+    np.testing.assert_array_equal(a.get_populations(), b.get_populations())
+    Fa, Ta = a.get_forces()
+    Fb, Tb = b.get_forces()
+    np.testing.assert_array_equal(Fa, Fb)
+    np.testing.assert_array_equal(Ta, Tb)
+    assert not np.any(Fa[1:5]) and np.any(Fa[0])
+    a.close()
+    b.close()
