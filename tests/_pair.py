@@ -33,6 +33,19 @@ def pop_rel_err(o, lat):
     return float(np.max(np.abs(Pg - Po) / np.abs(Po)))
 
 
+def pop_weight_err(o, lat):
+    """max over fluid nodes and directions of |P_gpu - P_ref| / (w_i rho0):
+    the error on the scale of each direction's population.  For 16-bit
+    storage, whose rounding is a fraction of the deviation from w_i rho0, this
+    stays meaningful where a population itself comes near zero."""
+    import oracle
+    _, w, _ = oracle.tables()
+    m = o.fluid_mask()
+    Po = o.populations()[:, m]
+    Pg = lat.get_populations()[:, m]
+    return float(np.max(np.abs(Pg - Po) / (w[:, None] * o.rho0)))
+
+
 def force_rel_err(o, lat):
     """max_b |F_gpu,b - F_ref,b| / max_b |F_ref,b|, same for torques (spheres
     and walls together, in the library's order)."""

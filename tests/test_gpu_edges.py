@@ -123,15 +123,7 @@ def test_surface_ties_decided_like_the_oracle(torch_stream):
     lat.close()
 
 
-@pytest.mark.parametrize("seed,halfway", [(1, False), (2, True), (3, False)])
-def test_random_geometry_parity(torch_stream, seed, halfway):
-    """Random small lattices: a few wall slabs and blocks (static and moving),
-    spheres on a 0.1 grid (near-ties), overlaps allowed, drift with rotation;
-    the same bars as the step.  Sphere speeds stay at most 0.1 per component
-    (lattice Mach number well below 1, the method's regime): at speeds near
-    0.35 some populations next to a sphere fall to about 1e-3 of their weight,
-    and a relative bar on them would measure FP32 rounding of the larger
-    populations they are made from."""
+def _random_case(seed):
     rng = np.random.Generator(np.random.PCG64(100 + seed))
     nx, ny, nz = (int(v) for v in rng.integers(18, 34, 3))
     w = np.zeros((nz, ny, nx), np.uint8)
@@ -143,11 +135,46 @@ def test_random_geometry_parity(torch_stream, seed, halfway):
     nb = int(rng.integers(4, 12))
     X = np.round(rng.uniform(0, 1, (nb, 3)) * [nx, ny, nz], 1) % [nx, ny, nz]
     R = rng.integers(4, 11, nb) * 0.5
-    case = W.Case(name=f"random_{seed}", nx=nx, ny=ny, nz=nz, tau0=float(rng.uniform(0.55, 0.9)),
+    return W.Case(name=f"random_{seed}", nx=nx, ny=ny, nz=nz, tau0=float(rng.uniform(0.55, 0.9)),
                   smag_c=float(rng.uniform(0.0, 0.2)), body_force=tuple(rng.normal(0, 2e-6, 3)),
                   wall_id=w, wall_vel=rng.normal(0, 0.01, (n_walls, 3)), wall_ref=rng.uniform(0, 20, (n_walls, 3)),
                   X=X, V=rng.integers(-2, 3, (nb, 3)) * 0.05, Omega=rng.normal(0, 0.005, (nb, 3)), R=R,
                   u_init=rng.normal(0.0, 0.01, (3, nz, ny, nx)), drift=True)
+
+
+@pytest.mark.parametrize("seed,storage,pop_bar,force_bar", [(1, "f16", 5e-3, 2e-2), (3, "bf16", 4e-2, 1e-1)])
+def test_random_geometry_reduced_precision(torch_stream, seed, storage, pop_bar, force_bar):
+    """The random lattices with 16-bit population storage.  Each store
+    rounds a deviation g = f - w rho0 to half a unit in its last place,
+    2^-12 |g| (FP16) or 2^-9 |g| (BF16); with |g| up to about 0.04 next to
+    the fastest spheres that is 3e-4 and 3e-3 of the smallest weight (1/36),
+    and over 15 steps it grows like a random walk by about 4.  The bars, on
+    the population error in units of each direction's weight (a relative
+    error per population is ill-conditioned where a population comes near
+    zero beside a fast sphere), are 5e-3 and 4e-2; on the norm-relative
+    forces 2e-2 and 1e-1.  The owner maps stay bit for bit."""
+    from ._pair import pop_weight_err
+    case = _random_case(seed)
+    o, lat = make_pair(case, storage=storage, stream=torch_stream)
+    advance(o, lat, case, 0, 15)
+    np.testing.assert_array_equal(lat.get_owner(), o.owner())
+    pe = pop_weight_err(o, lat)
+    fe, te = force_rel_err(o, lat)
+    print(f"pop/w {pe:.2e}  F {fe:.2e}  T {te:.2e}")
+    assert pe <= pop_bar and fe <= force_bar and te <= force_bar
+    lat.close()
+
+
+@pytest.mark.parametrize("seed,halfway", [(1, False), (2, True), (3, False)])
+def test_random_geometry_parity(torch_stream, seed, halfway):
+    """Random small lattices: a few wall slabs and blocks (static and moving),
+    spheres on a 0.1 grid (near-ties), overlaps allowed, drift with rotation;
+    the same bars as the step.  Sphere speeds stay at most 0.1 per component
+    (lattice Mach number well below 1, the method's regime): at speeds near
+    0.35 some populations next to a sphere fall to about 1e-3 of their weight,
+    and a relative bar on them would measure FP32 rounding of the larger
+    populations they are made from."""
+    case = _random_case(seed)
     o, lat = make_pair(case, halfway=halfway, stream=torch_stream)
     np.testing.assert_array_equal(lat.get_owner(), o.owner())
     advance(o, lat, case, 0, 15)
