@@ -169,3 +169,26 @@ def test_zieb_plane_wider_than_the_reduction_grid(torch_stream):
     assert rho == pytest.approx(o.zieb["rho"], rel=1e-6)
     assert vf == pytest.approx(o.zieb["vf"], abs=1e-7)
     lat.close()
+
+
+@pytest.mark.parametrize("storage,pop_bar,rho_bar", [("f16", 5e-3, 1e-4), ("bf16", 4e-2, 1e-3)])
+def test_zieb_reduced_precision(torch_stream, storage, pop_bar, rho_bar):
+    """The inflow plane with 16-bit population storage, 30 steps.  Each
+    store rounds a deviation to half a unit in its last place (2^-12 and
+    2^-9 of it, up to 3e-4 and 3e-3 of the smallest weight), growing about
+    like the square root of the step count: bars of 5e-3 and 4e-2 on the
+    populations in units of each direction's weight.  The cylinder density
+    comes from the mean over the plane's nodes, where the roundings average
+    out: 1e-4 and 1e-3 relative."""
+    from ._pair import pop_weight_err
+    o, lat, case, _ = _pair(torch_stream, storage=storage)
+    for n in range(30):
+        o.step(1)
+        lat.step(1)
+    pe = pop_weight_err(o, lat)
+    rho, H, vf = lat.zieb_state()
+    print(f"{storage}: pop/w {pe:.2e} rho {rho:.8f} (oracle {o.zieb['rho']:.8f})")
+    assert pe <= pop_bar
+    assert rho == pytest.approx(o.zieb["rho"], rel=rho_bar)
+    assert H == pytest.approx(o.zieb["H"], rel=1e-12)
+    lat.close()
