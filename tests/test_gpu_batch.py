@@ -78,7 +78,7 @@ def test_autotune_leaves_state_and_uses_cache(torch_stream, tmp_path):
     lat2.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 def test_batch_matches_single_lattices(torch_stream, storage):
     from paper_1703_05158_amd import Batch
     single = _build(torch_stream, storage)
