@@ -34,12 +34,13 @@ def _build(stream, storage="f32"):
     return [Lattice.from_case(c, storage=storage, bb_mode=bb, stream=stream) for c, bb in _members()]
 
 
-def test_tile_shapes_bitwise(torch_stream):
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_tile_shapes_bitwise(torch_stream, storage):
     from paper_1703_05158_amd import TILE_SHAPES, Lattice
     case, _ = _members()[1]
     ref = None
     for shape in range(len(TILE_SHAPES)):
-        lat = Lattice.from_case(case, stream=torch_stream)
+        lat = Lattice.from_case(case, storage=storage, stream=torch_stream)
         lat.set_tile(shape)
         assert lat.tile == shape
         lat.step(6)
