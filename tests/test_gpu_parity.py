@@ -229,11 +229,12 @@ def test_mass_and_momentum_balance_gpu(torch_stream):
     lat.close()
 
 
-def test_state_checkpoint_resume_bitwise(torch_stream):
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_state_checkpoint_resume_bitwise(torch_stream, storage):
     case = W.case_box(n=(30, 30, 30), n_spheres=5, radius=(2.0, 4.0), v_sigma=0.02, w_sigma=0.01,
                       seed=6, drift=True)
     from paper_1703_05158_amd import Lattice
-    lat = Lattice.from_case(case, stream=torch_stream)
+    lat = Lattice.from_case(case, storage=storage, stream=torch_stream)
 
     def run(l, a, b):
         for n in range(a, b):
@@ -243,7 +244,7 @@ def test_state_checkpoint_resume_bitwise(torch_stream):
     state = lat.get_state()
     run(lat, 6, 12)
     ref = lat.get_populations()
-    lat2 = Lattice.from_case(case, stream=torch_stream)
+    lat2 = Lattice.from_case(case, storage=storage, stream=torch_stream)
     lat2.set_state(state)
     run(lat2, 6, 12)
     np.testing.assert_array_equal(lat2.get_populations(), ref)
