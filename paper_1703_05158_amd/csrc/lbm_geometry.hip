@@ -39,6 +39,50 @@ __device__ __forceinline__ void for_box(const Box &bx, int nx, int ny, int nz, F
     }
 }
 
+// Offset of box coordinate v from centre coordinate c in FP32, folded to
+// the nearest periodic image.
+__device__ __forceinline__ float foff(int v, double c, int n)
+{
+    const float d = (float)((double)v - c);
+    return d > 0.5f * (float)n ? d - (float)n : (d < -0.5f * (float)n ? d + (float)n : d);
+}
+
+// The nodes of old ball B's box with the (8, 8, 4) workgroup, skipping those
+// surely outside B and, when keeps, those surely inside the new ball Bn:
+// FP32 offsets with a margin that covers their rounding (the exact FP64
+// tests are left to f, which sees every node either test could accept).
+template <typename F>
+__device__ __forceinline__ void walk_leaving(const double *B, const double *Bn, bool keeps, int nx, int ny, int nz,
+                                             F &&f)
+{
+    const Box bx = body_box(B, 0);
+    const float R2 = (float)(B[9] * B[9]);
+    const float out2 = R2 + 0.01f + 1e-5f * R2;
+    const float Rn2 = keeps ? (float)(Bn[9] * Bn[9]) : 0.0f;
+    const float in2 = keeps ? Rn2 - (0.01f + 1e-5f * Rn2) : -1.0f;
+    const double cx = keeps ? Bn[0] : 0.0, cy = keeps ? Bn[1] : 0.0, cz = keeps ? Bn[2] : 0.0;
+    for (int kz = threadIdx.z; kz < bx.ez; kz += 4) {
+        const int vz = bx.z0 + kz, pz = wrap1(vz, nz);
+        const float dz = foff(vz, B[2], nz), ez = foff(vz, cz, nz);
+        for (int ky = threadIdx.y; ky < bx.ey; ky += 8) {
+            const int vy = bx.y0 + ky, py = wrap1(vy, ny);
+            const float dy = foff(vy, B[1], ny), ey = foff(vy, cy, ny);
+            const float dyz = dy * dy + dz * dz, eyz = ey * ey + ez * ez;
+            for (int kx = threadIdx.x; kx < bx.ex; kx += 8) {
+                const int vx = bx.x0 + kx;
+                const float dx = foff(vx, B[0], nx);
+                if (dx * dx + dyz > out2) continue;
+                if (keeps) {
+                    const float ex = foff(vx, cx, nx);
+                    if (ex * ex + eyz < in2) continue;
+                }
+                const int px = wrap1(vx, nx);
+                f(px, py, pz, px + nx * (py + ny * pz));
+            }
+        }
+    }
+}
+
 constexpr int kBoxU = 8;  // box nodes per thread whose owner loads are in flight together
 
 // Node k (x fastest) of a body's box: its coordinates and index.
@@ -119,7 +163,9 @@ __global__ __launch_bounds__(kBlock) void k_vacate(GeomArgs g)
     const uint16_t id = (uint16_t)(g.n_walls + b);
     uint16_t *own = g.own;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
-    for_box(body_box(B, 0), nx, ny, nz, [&](int px, int py, int pz, int n) {
+    // a node the sphere owns lies inside its old ball; one surely inside the
+    // new ball stays owned
+    walk_leaving(B, Bn, keeps, nx, ny, nz, [&](int px, int py, int pz, int n) {
         if (own[n] == id && !(keeps && inside(Bn, px, py, pz, nx, ny, nz))) own[n] = (uint16_t)(kVacated | id);
     });
 }
