@@ -11,9 +11,12 @@ re-rasterises the spheres and runs the fused step, and the per-body force and
 torque are copied into a device history buffer (the DEM consumes them every
 step).  Inputs are resident in HBM before the timed region starts.
 
-Prints one JSON line: MLUPS (all nodes) over the timed steps, the roofline
-of the dominant kernel (the fused step) from HIP events on its stream and the
-algorithmic bytes per launch, and the FP64 CPU oracle timed on a bounded
+Prints one JSON line: MLUPS (all nodes) over the timed steps; the roofline
+of the dominant kernel (the fused step kernel: boundary links, streaming,
+collision) from HIP events on its stream and its algorithmic bytes per
+launch (`frac`), and of the whole step (`frac_step`: the same bytes over the
+wall-clock time per step), with the time of every part of the step from HIP
+events in the same timed run; and the FP64 CPU oracle timed on a bounded
 sample of the same workload on the host cores.
 """
 import argparse
@@ -28,10 +31,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 METRIC = "MLUPS and % of HBM roofline; mixed-precision vs FP32 at stated error"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_piston_duct_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_piston_duct_traffic.json")
 # the step kernel's source and the headers it is compiled with
 KERNEL_SRC = [os.path.join(ROOT, "paper_1703_05158_amd", "csrc", f)
-              for f in ("lbm_step.hip", "lbm_device.h", "lbm_internal.h")]
+              for f in ("lbm_fused.hip", "lbm_collide.h", "lbm_linkmath.h", "lbm_device.h", "lbm_internal.h")]
 TRAFFIC_WORKLOAD = "piston_duct_128x128x512_4000spheres_drift"
 REFERENCE = os.path.join(ROOT, "tests", "golden", "duct_reference.npz")
 
@@ -86,17 +89,17 @@ def record_traffic(d):
         for c in ("fetch", "write"):
             m = {}
             for k, v in _counters(os.path.join(d, f"pb_{c}_{st}")).items():
-                g = re.search(rf"k_step<{sv}, (\d+), (\d+), (\d+)>", k)
+                g = re.search(rf"k_fused<{sv}, (\d+), (\d+), (\d+)>", k)
                 if g:
                     m["x".join(g.groups())] = sum(v.values()) / len(v)
             per.append(m)
         tiles = sorted(set(per[0]) & set(per[1]))
         if not tiles:
-            raise SystemExit(f"no k_step<{sv},...> kernel in both pb_fetch_{st} and pb_write_{st}")
+            raise SystemExit(f"no k_fused<{sv},...> kernel in both pb_fetch_{st} and pb_write_{st}")
         out[st] = {"kernel_sha": kernel_sha(), "workload": TRAFFIC_WORKLOAD,
                    "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
                    "commands": [cmd.format(c="FETCH_SIZE", s=st), cmd.format(c="WRITE_SIZE", s=st)],
-                   "tiles": {t: {"kernel": f"k_step<{sv},{t.replace('x', ',')}>",
+                   "tiles": {t: {"kernel": f"k_fused<{sv},{t.replace('x', ',')}>",
                                  "fetch_kib_per_dispatch": round(per[0][t], 1),
                                  "write_kib_per_dispatch": round(per[1][t], 1),
                                  "bytes_per_launch": round(per[0][t] * 1024 * fs + per[1][t] * 1024 * ws)}
@@ -283,7 +286,8 @@ def main():
             r = timed_run(case, st, K, Wm)
             mixed[st] = {"value": r["value"], "unit": "MLUPS", "ms_per_step": r["ms_per_step"],
                          "speedup_vs_f32": round(r["value"] / main_run["value"], 3),
-                         "kernel_ms": r["roofline"]["kernel_ms"], "roofline_frac": r["roofline"]["frac"]}
+                         "kernel_ms": r["roofline"]["kernel_ms"], "roofline_frac": r["roofline"]["frac"],
+                         "roofline_frac_step": r["roofline"]["frac_step"]}
         errs = precision_errors(case)
         if errs:
             for st, e in errs.items():
@@ -484,7 +488,8 @@ def timed_run(case, storage, K, Wm):
         lat.get_forces_device(hist[n])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    kms, launches = lat.profile_read()
+    parts, launches = lat.profile_read_parts()
+    kms = parts["step"]
     lat.profile(False)
     n_fluid_end = lat.count_fluid()
     assert torch.isfinite(hist).all().item()
@@ -527,18 +532,25 @@ def timed_run(case, storage, K, Wm):
     N = case.n_nodes
     sbytes = 4 if storage == "f32" else 2
     nf = 0.5 * (n_fluid + n_fluid_end)
-    # algorithmic bytes of one step-kernel launch: every fluid node reads and
-    # writes 19 populations; every node's owner code (2 B) is read once
+    # algorithmic bytes of one step (and of one launch of the fused step
+    # kernel, which does all of it but the re-rasterisation): every fluid
+    # node reads and writes 19 populations; every node's owner code (2 B) is
+    # read once
     alg_bytes = 2 * 19 * sbytes * nf + 2 * N
     k_avg_s = kms / launches * 1e-3
     achieved = alg_bytes / k_avg_s / 1e9
+    step_s = dt / K
     traffic = measured_traffic(storage, TILE_SHAPES[shape])
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
+            "frac_step": round(alg_bytes / step_s / 1e9 / HBM_PEAK_GBS, 4),
+            "step_achieved": round(alg_bytes / step_s / 1e9, 1),
             "frac_measured": None if traffic is None else round(traffic / k_avg_s / 1e9 / HBM_PEAK_GBS, 4),
             "kernel_mlups": round(N / k_avg_s / 1e6, 1),
-            "kernel": f"k_step<{storage}>", "kernel_ms": round(k_avg_s * 1e3, 4),
+            "kernel": f"k_fused<{storage},{TILE_SHAPES[shape].replace('x', ',')}>",
+            "kernel_ms": round(k_avg_s * 1e3, 4),
+            "parts_ms_per_step": {k: round(v / launches, 4) for k, v in parts.items()},
             "tile": TILE_SHAPES[shape], "tile_us": {TILE_SHAPES[i]: round(float(t), 1) for i, t in enumerate(shape_us)},
             "alg_bytes_per_launch": int(alg_bytes)}
     return {"value": round(N * K / dt / 1e6, 1), "ms_per_step": round(dt / K * 1e3, 4),

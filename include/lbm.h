@@ -58,8 +58,8 @@ typedef enum {
 } lbm_status;
 
 /* Storage of the populations in HBM.  All three store deviations
- * g_i = f_i - w_i rho0 from the rest state; collision math is FP32 and the
- * force/torque sums FP64 in every mode. */
+ * g_i = f_i - w_i rho0 from the rest state; collision math is FP32 and each
+ * link's force and torque FP64 in every mode. */
 typedef enum {
     LBM_STORE_F32 = 0,     /* 4 bytes per population */
     LBM_STORE_F16_DEV = 1, /* IEEE binary16 deviations, 2 bytes */
@@ -156,13 +156,21 @@ lbm_status lbm_set_bodies_device(lbm_handle h, int32_t n, const double *d_table)
 lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *u);
 
 /* Advance nsteps steps, asynchronously on the handle's stream.  Each step:
- * re-rasterise the spheres if they were set since the previous step; the
- * link pass closes every cut link with interpolated bounce-back and the
- * moving-boundary term (Sec. 2.3), writing the value into the solid node's
- * slot of the current state, and reduces the momentum exchange per body
- * (force and torque); the step kernel then does pull streaming, moments,
- * Smagorinsky tau*, BGK + Guo collision and the store (Sec. 2.2).  Forces
- * are those of the last step.
+ * re-rasterise the spheres if they were set since the previous step (nodes
+ * a sphere no longer covers are refilled, then the new spheres are
+ * stamped); then, on the fused path (the default), one kernel per tile
+ * closes every cut link of the tile's fluid nodes with interpolated
+ * bounce-back and the moving-boundary term (Sec. 2.3), formed from the
+ * current state, adds the momentum exchanged on each link to the body's
+ * force and torque, and does pull streaming, moments, Smagorinsky tau*,
+ * BGK + Guo collision and the store (Sec. 2.2).  The force and torque sums
+ * are kept as 64-bit fixed point with a resolution of 2^-32 per link
+ * contribution (sums must stay below 2^31 in magnitude), so they are the same
+ * bit for bit in any launch order, tile shape or batch.  On the split path
+ * (lbm_set_step_path) a link pass writes every link value into the solid
+ * node's slot of the current state and reduces the forces per body in FP64,
+ * then the pull-collide kernel pulls it; the populations are the same bit
+ * for bit on both paths.  Forces are those of the last step.
  * With nan_guard_every = k the call synchronises every k steps and returns
  * LBM_ERR_UNSTABLE if a fluid node had a non-finite or non-positive density
  * or a non-finite velocity.  Errors: STATE (before lbm_init_fields), ARG
@@ -218,13 +226,36 @@ lbm_status lbm_get_info(lbm_handle h, lbm_info *info);
  * the owner map; synchronises).  Errors: ARG, HIP. */
 lbm_status lbm_count_fluid(lbm_handle h, int64_t *n_fluid);
 
-/* Timing of the fused step kernel with HIP events on the handle's stream:
- * lbm_profile(h, 1) starts recording an event pair around every step-kernel
- * launch (and clears earlier records), lbm_profile(h, 0) stops.
- * lbm_profile_read synchronises and returns the summed kernel time in
- * milliseconds and the number of launches recorded.  Errors: ARG, HIP. */
+/* Timing of the step's parts with HIP events on the handle's stream:
+ * lbm_profile(h, 1) starts recording events at the boundaries of the parts
+ * of every step (and clears earlier records), lbm_profile(h, 0) stops.
+ * lbm_profile_read synchronises and returns the summed time of the step
+ * kernel (the fused kernel, or the pull-collide kernel of the split path) in
+ * milliseconds and the number of steps recorded.  lbm_profile_read_parts
+ * returns ms[LBM_PROF_PARTS]: the summed time of each part below over the
+ * recorded steps (0 for a part the path does not run), and the step count.
+ * Errors: ARG, HIP. */
+enum {
+    LBM_PROF_GEOMETRY = 0, /* inflow-plane update and re-rasterisation */
+    LBM_PROF_LINKS = 1,    /* boundary-link pass (split path) */
+    LBM_PROF_STEP = 2,     /* step kernel */
+    LBM_PROF_FORCES = 3,   /* force finish (fused path) */
+    LBM_PROF_WHOLE = 4,    /* the whole step, first event to last */
+    LBM_PROF_PARTS = 5
+};
 lbm_status lbm_profile(lbm_handle h, int32_t enable);
 lbm_status lbm_profile_read(lbm_handle h, double *ms_total, int64_t *launches);
+lbm_status lbm_profile_read_parts(lbm_handle h, double *ms, int64_t *steps);
+
+/* Kernels that make a step (see lbm_step).  FUSED: one kernel per step does
+ * links, streaming and collision, then a small kernel turns the fixed-point
+ * force sums into FP64.  SPLIT: the boundary-link pass, then the
+ * pull-collide kernel.  Both give the same populations bit for bit; their
+ * forces agree to rounding.  The drag gradient's reverse sweep uses the
+ * split path's kernels whatever the setting.  Errors: ARG. */
+typedef enum { LBM_PATH_FUSED = 0, LBM_PATH_SPLIT = 1 } lbm_step_path;
+lbm_status lbm_set_step_path(lbm_handle h, int32_t path);
+lbm_status lbm_get_step_path(lbm_handle h, int32_t *path);
 
 /* Zoom-in with Effective Boundaries (Sec. 2.6): the plane z = z_s is fed
  * by a removed cylinder of volume `volume` and piston area `area` whose
@@ -291,17 +322,19 @@ lbm_status lbm_autotune_tile(lbm_handle h, int32_t trial_steps, const char *cach
                              double *us);
 
 /* Batched stepping of independent lattices (a parameter sweep of many
- * boxes): every step of the batch is one replay of a captured hipGraph that
- * runs the link pass of all members as one launch over their spheres and
- * wall-link chunks, the wall totals, the step kernel of all members as one
- * persistent launch over their tiles (each member with its own
- * parameters), and a parity flip.  Each member's results
- * are bit for bit those of lbm_step on that member.
+ * boxes): a batched step runs the fused step of all members as one
+ * persistent launch over their tiles (each member with its own parameters),
+ * the force finish of all members, and a parity flip.  lbm_batch_step
+ * replays a captured hipGraph of 50 such steps as long as at least 50
+ * remain, then a graph of one step for the rest.  Each member's results are
+ * bit for bit those of lbm_step on that member.
  *   members : n distinct handles, all past lbm_init_fields, same storage,
  *             no bodies set since their last step (their own tile shapes
  *             do not matter: the batch has one, see below).  The batch borrows them:
- *             they must outlive it, and their bodies and walls must not
- *             change while it is used (build a new batch after a change).
+ *             they must outlive it, and their bodies, walls, body force
+ *             and state must not be replaced while it is used (build a new
+ *             batch after a change; lbm_batch_step refuses a member
+ *             changed since the batch was built with STATE).
  *   stream  : hipStream_t for the batch's work, or NULL for a stream of its
  *             own (default priority).
  * lbm_batch_step waits for the members' queued work, replays the graph

@@ -24,7 +24,8 @@ __all__ = [
     "lbm_step", "lbm_get_forces", "lbm_get_forces_device", "lbm_get_populations",
     "lbm_set_populations", "lbm_get_macro", "lbm_get_owner", "lbm_get_state",
     "lbm_set_state", "lbm_get_info", "lbm_count_fluid", "lbm_profile", "lbm_profile_read",
-    "STORAGE", "BB_MODE", "LIB_PATH",
+    "lbm_profile_read_parts", "lbm_set_step_path", "lbm_get_step_path",
+    "STORAGE", "BB_MODE", "STEP_PATH", "PROF_PARTS", "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbm.so")
@@ -33,6 +34,8 @@ STATUS = {0: "LBM_OK", 1: "LBM_ERR_ARG", 2: "LBM_ERR_OOM", 3: "LBM_ERR_HIP",
           4: "LBM_ERR_STATE", 5: "LBM_ERR_UNSTABLE", 6: "LBM_ERR_CAPACITY"}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 BB_MODE = {"bouzidi": 0, "halfway": 1}
+STEP_PATH = {"fused": 0, "split": 1}
+PROF_PARTS = ("geometry", "links", "step", "forces", "whole")
 
 
 class LBMError(RuntimeError):
@@ -85,6 +88,9 @@ _sig = {
     "lbm_count_fluid": (ct.c_int, [_H, ct.POINTER(ct.c_int64)]),
     "lbm_profile": (ct.c_int, [_H, ct.c_int32]),
     "lbm_profile_read": (ct.c_int, [_H, _dp, ct.POINTER(ct.c_int64)]),
+    "lbm_profile_read_parts": (ct.c_int, [_H, _dp, ct.POINTER(ct.c_int64)]),
+    "lbm_set_step_path": (ct.c_int, [_H, ct.c_int32]),
+    "lbm_get_step_path": (ct.c_int, [_H, ct.POINTER(ct.c_int32)]),
     "lbm_set_zieb": (ct.c_int, [_H, ct.c_int32, ct.c_double, ct.c_double, ct.c_double]),
     "lbm_get_zieb": (ct.c_int, [_H, _dp]),
     "lbm_set_body_force": (ct.c_int, [_H, ct.c_void_p]),
@@ -285,6 +291,24 @@ def lbm_profile_read(h):
     return ms.value, n.value
 
 
+def lbm_profile_read_parts(h):
+    """({part: summed milliseconds} for the parts of PROF_PARTS, steps recorded)."""
+    ms = (ct.c_double * len(PROF_PARTS))()
+    n = ct.c_int64(0)
+    _check(h, _L.lbm_profile_read_parts(h, ms, ct.byref(n)))
+    return dict(zip(PROF_PARTS, list(ms))), n.value
+
+
+def lbm_set_step_path(h, path) -> None:
+    _check(h, _L.lbm_set_step_path(h, STEP_PATH[path] if isinstance(path, str) else int(path)))
+
+
+def lbm_get_step_path(h) -> str:
+    p = ct.c_int32(0)
+    _check(h, _L.lbm_get_step_path(h, ct.byref(p)))
+    return {v: k for k, v in STEP_PATH.items()}[p.value]
+
+
 def lbm_set_zieb(h, z_s, area, volume, v_piston) -> None:
     _check(h, _L.lbm_set_zieb(h, int(z_s), float(area), float(volume), float(v_piston)))
 
@@ -388,13 +412,15 @@ class Lattice:
 
     @classmethod
     def from_case(cls, case, storage="f32", bb_mode="bouzidi", stream=None, max_bodies=None,
-                  nan_guard_every=0, init=True):
+                  nan_guard_every=0, init=True, path=None):
         nw = case.n_walls
         cfg = config(case.nx, case.ny, case.nz, case.tau0, case.smag_c, case.rho0, case.body_force,
                      storage=storage, bb_mode=bb_mode,
                      max_bodies=case.n_bodies if max_bodies is None else max_bodies,
                      max_walls=nw, nan_guard_every=nan_guard_every, stream=stream)
         lat = cls(cfg)
+        if path is not None:
+            lat.set_step_path(path)
         if case.wall_id is not None:
             lat.set_walls(case.wall_id, case.wall_vel, case.wall_ref)
         lat.set_bodies(*case.bodies_at(0))
@@ -468,6 +494,16 @@ class Lattice:
 
     def profile_read(self):
         return lbm_profile_read(self.h)
+
+    def profile_read_parts(self):
+        return lbm_profile_read_parts(self.h)
+
+    def set_step_path(self, path):
+        lbm_set_step_path(self.h, path)
+
+    @property
+    def step_path(self):
+        return lbm_get_step_path(self.h)
 
     def set_zieb(self, z_s, area, volume, v_piston):
         lbm_set_zieb(self.h, z_s, area, volume, v_piston)

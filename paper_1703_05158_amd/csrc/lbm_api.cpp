@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -40,6 +41,9 @@ struct lbm_ctx {
     double *walls = nullptr;
     int n_walls = 0;
     double *acc = nullptr;             // (max_bodies + max_walls) * 6: forces of the last step
+    unsigned long long *fsum = nullptr; // fused step: fixed-point sums, (max_bodies + max_walls * kWallRep) * 6
+    int path = LBM_PATH_FUSED;         // lbm_step_path
+    uint64_t geom_gen = 0;             // bumped whenever the geometry, the body force or the state is replaced
     int tile = kTile64x2x2;            // TileShape of the step kernel
     int ntx = 0, nty = 0, ntz = 0, n_tiles = 0;
     // wall links (fixed while the walls are): fluid nodes per (wall, direction),
@@ -69,7 +73,12 @@ struct lbm_ctx {
     int steps_done = 0;
     int64_t device_bytes = 0;
     bool prof = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+    // profiling: per step, events at the start, after the geometry update,
+    // after the link pass (split path), after the step kernel and after the
+    // force finish; events come from a pool that lives as long as the handle
+    std::vector<std::array<hipEvent_t, 5>> prof_ev;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
     std::string err;
 };
 
@@ -216,6 +225,59 @@ LinkArgs link_args(const lbm_ctx *h)
     return la;
 }
 
+size_t fsum_entries(const lbm_config &c) { return 6 * ((size_t)c.max_bodies + (size_t)c.max_walls * kWallRep); }
+
+FusedArgs fused_args(const lbm_ctx *h)
+{
+    FusedArgs f{};
+    f.s = step_args(h);
+    f.n_walls = h->n_walls;
+    f.nb = h->nb_state;
+    f.halfway = h->cfg.bb_mode == LBM_BB_HALFWAY;
+    f.bodies = h->tab[h->ts];
+    f.walls = h->walls;
+    f.fsum = h->fsum;
+    f.wall_base = h->cfg.max_bodies;
+    return f;
+}
+
+FinishArgs finish_args(const lbm_ctx *h)
+{
+    FinishArgs fa{};
+    fa.fsum = h->fsum;
+    fa.wall_base = h->cfg.max_bodies;
+    fa.nb = h->nb_state;
+    fa.n_walls = h->n_walls;
+    fa.out = h->acc;
+    return fa;
+}
+
+// An event of the handle's pool for the profile of one step.
+hipError_t prof_event(lbm_ctx *h, hipEvent_t *e)
+{
+    if (h->ev_used == h->ev_pool.size()) {
+        hipEvent_t ne = nullptr;
+        const hipError_t r = hipEventCreate(&ne);
+        if (r != hipSuccess) return r;
+        h->ev_pool.push_back(ne);
+    }
+    *e = h->ev_pool[h->ev_used++];
+    return hipSuccess;
+}
+
+hipError_t prof_mark(lbm_ctx *h, hipEvent_t *e)
+{
+    const hipError_t r = prof_event(h, e);
+    return r != hipSuccess ? r : hipEventRecord(*e, h->stream);
+}
+
+// The NaN guard's flag cleared on the handle's stream (after a state change).
+lbm_status clear_flag(lbm_ctx *h)
+{
+    HIP_TRY(h, hipMemsetAsync(h->flag, 0, sizeof(int), h->stream));
+    return LBM_OK;
+}
+
 // Rebuild the whole owner map: walls, then the spheres of tab[ts].
 lbm_status rasterize_full(lbm_ctx *h)
 {
@@ -236,12 +298,12 @@ lbm_status rasterize_update(lbm_ctx *h)
     GeomArgs vac = old_g;
     vac.bodies2 = new_g.bodies;
     vac.nb2 = new_g.nb;
-    HIP_TRY(h, launch_vacate(vac, h->stream));
+    HIP_TRY(h, launch_vacate(h->cfg.storage, vac, h->stream));
     HIP_TRY(h, launch_stamp(new_g, h->stream));
-    HIP_TRY(h, launch_settle(h->cfg.storage, old_g, h->stream));
     h->ts = 1 - h->ts;
     h->nb_state = h->nb_next;
     h->dirty = false;
+    h->geom_gen++;
     return LBM_OK;
 }
 
@@ -412,7 +474,7 @@ lbm_status build_wall_links(lbm_ctx *h, const uint8_t *wall, int n_walls)
 
 extern "C" {
 
-int32_t lbm_version(void) { return 10000; }
+int32_t lbm_version(void) { return 10100; }
 
 const char *lbm_last_error(lbm_handle h) { return h ? h->err.c_str() : kNullHandle; }
 
@@ -455,6 +517,7 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         dalloc(h, &h->tab[1], sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->walls, sizeof(double) * kWallStride * std::max(c.max_walls, 1)) != hipSuccess ||
         dalloc(h, &h->acc, sizeof(double) * 6 * std::max(nbt, 1)) != hipSuccess ||
+        dalloc(h, &h->fsum, sizeof(unsigned long long) * std::max(fsum_entries(c), (size_t)1)) != hipSuccess ||
         dalloc(h, &h->order, sizeof(int) * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->zstate, sizeof(ZiebState)) != hipSuccess ||
         dalloc(h, &h->zpart, sizeof(double) * (3 * kZiebMaxBlocks + 1)) != hipSuccess ||
@@ -470,6 +533,8 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         hipMemsetAsync(h->pop[0], 0, popb, h->stream) != hipSuccess ||
         hipMemsetAsync(h->pop[1], 0, popb, h->stream) != hipSuccess ||
         hipMemsetAsync(h->acc, 0, sizeof(double) * 6 * std::max(nbt, 1), h->stream) != hipSuccess ||
+        hipMemsetAsync(h->fsum, 0, sizeof(unsigned long long) * std::max(fsum_entries(c), (size_t)1), h->stream) !=
+            hipSuccess ||
         hipMemsetAsync(h->flag, 0, sizeof(int), h->stream) != hipSuccess ||
         hipMemsetAsync(h->zpart + 3 * kZiebMaxBlocks, 0, sizeof(double), h->stream) != hipSuccess)
         return bail(LBM_ERR_HIP);
@@ -483,13 +548,10 @@ void lbm_destroy(lbm_handle h)
 {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
-    for (auto &p : h->prof_ev) {
-        (void)hipEventDestroy(p.first);
-        (void)hipEventDestroy(p.second);
-    }
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     free_wall_links(h);
-    void *dev[] = {h->pop[0], h->pop[1], h->own, h->wall_map, h->tab[0], h->tab[1],
-                   h->walls, h->acc, h->order, h->flag, h->scratch, h->zstate, h->zpart};
+    void *dev[] = {h->pop[0], h->pop[1], h->own, h->wall_map, h->tab[0], h->tab[1], h->walls,
+                   h->acc, h->fsum, h->order, h->flag, h->scratch, h->zstate, h->zpart};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (h->pinned) (void)hipHostFree(h->pinned);
@@ -655,13 +717,64 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *u)
     GeomArgs g = geom(h);
     HIP_TRY(h, launch_init_pop(h->cfg.storage, g, rho_dev, u_dev, h->stream));
     HIP_TRY(h, launch_zero(h->acc, 6 * (h->cfg.max_bodies + h->cfg.max_walls), h->stream));
+    HIP_TRY(h, launch_zero_fix(h->fsum, (int)fsum_entries(h->cfg), h->stream));
+    TRY(clear_flag(h));
     const ZiebState z0{-1.0, 0.0, 0.0, 0.0};
     HIP_TRY(h, hipMemcpyAsync(h->zstate, &z0, sizeof z0, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->initialized = true;
     h->steps_done = 0;
+    h->geom_gen++;
     return LBM_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// One step of the handle: inflow-plane update, re-rasterisation when the
+// bodies changed, then the fused step kernel and the force finish, or (the
+// split path) the boundary-link pass and the pull-collide kernel.
+lbm_status step_once(lbm_ctx *h)
+{
+    const lbm_config &c = h->cfg;
+    std::array<hipEvent_t, 5> ev{};
+    if (h->prof) HIP_TRY(h, prof_mark(h, &ev[0]));
+    // the inflow plane's mean velocity is that of the current state, on its
+    // own geometry: taken before the spheres of this step are drawn
+    if (h->zieb_z >= 0) HIP_TRY(h, launch_zieb_update(c.storage, zieb_args(h), h->stream));
+    if (h->dirty) TRY(rasterize_update(h));
+    if (h->prof) HIP_TRY(h, prof_mark(h, &ev[1]));
+    if (h->path == LBM_PATH_FUSED) {
+        ev[2] = ev[1];
+        HIP_TRY(h, launch_fused(c.storage, fused_args(h), h->stream));
+        if (h->prof) HIP_TRY(h, prof_mark(h, &ev[3]));
+        HIP_TRY(h, launch_finish(finish_args(h), h->stream));
+        if (h->prof) HIP_TRY(h, prof_mark(h, &ev[4]));
+    } else {
+        LinkArgs la = link_args(h);
+        HIP_TRY(h, launch_links(c.storage, la, h->stream));
+        if (h->prof) HIP_TRY(h, prof_mark(h, &ev[2]));
+        // the step kernel's first workgroups add up the wall chunks
+        StepArgs a = step_args(h);
+        a.n_wsum = la.n_walls;
+        a.wsum_nb = la.nb;
+        a.wsum_part = h->wl_part;
+        a.wsum_wblk = h->wl_wblk;
+        a.wsum_out = h->acc;
+        HIP_TRY(h, launch_step(c.storage, a, h->stream));
+        if (h->prof) HIP_TRY(h, prof_mark(h, &ev[3]));
+        ev[4] = ev[3];
+    }
+    if (h->prof) h->prof_ev.push_back(ev);
+    h->cur = 1 - h->cur;
+    h->steps_done++;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 lbm_status lbm_step(lbm_handle h, int32_t nsteps)
 {
@@ -670,41 +783,8 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
     lbm_status st = check_ready(h);
     if (st != LBM_OK) return st;
     const lbm_config &c = h->cfg;
-    StepArgs a = step_args(h);
-    LinkArgs la = link_args(h);
     for (int s = 0; s < nsteps; ++s) {
-        // the inflow plane's mean velocity is that of the current state, on
-        // its own geometry: taken before the spheres of this step are drawn
-        if (h->zieb_z >= 0) HIP_TRY(h, launch_zieb_update(c.storage, zieb_args(h), h->stream));
-        if (h->dirty && (st = rasterize_update(h)) != LBM_OK) return st;
-        la.n_walls = h->n_walls;
-        la.n_wblk = h->n_walls > 0 ? h->n_wblk : 0;
-        la.nb = h->nb_state;
-        la.order = h->n_order == h->nb_state ? h->order : nullptr;
-        la.bodies = h->tab[h->ts];
-        la.pop = h->pop[h->cur];
-        HIP_TRY(h, launch_links(c.storage, la, h->stream));
-        // the step kernel's first workgroups add up the wall chunks
-        a.n_wsum = la.n_walls;
-        a.wsum_nb = la.nb;
-        a.wsum_part = h->wl_part;
-        a.wsum_wblk = h->wl_wblk;
-        a.wsum_out = h->acc;
-        a.src = h->pop[h->cur];
-        a.dst = h->pop[1 - h->cur];
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (h->prof) {
-            HIP_TRY(h, hipEventCreate(&e0));
-            HIP_TRY(h, hipEventCreate(&e1));
-            HIP_TRY(h, hipEventRecord(e0, h->stream));
-        }
-        HIP_TRY(h, launch_step(c.storage, a, h->stream));
-        if (h->prof) {
-            HIP_TRY(h, hipEventRecord(e1, h->stream));
-            h->prof_ev.emplace_back(e0, e1);
-        }
-        h->cur = 1 - h->cur;
-        h->steps_done++;
+        TRY(step_once(h));
         if (c.nan_guard_every > 0 && (h->steps_done % c.nan_guard_every == 0 || s == nsteps - 1)) {
             HIP_TRY(h, hipMemcpyAsync(h->flag_host, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
             HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -775,6 +855,7 @@ lbm_status lbm_set_populations(lbm_handle h, const double *f)
         HIP_TRY(h, launch_import_pop(h->cfg.storage, h->N, h->Ns, i, (float)h->cfg.rho0, h->scratch, h->pop[h->cur],
                                      h->stream));
     }
+    TRY(clear_flag(h));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
 }
@@ -889,6 +970,17 @@ lbm_status lbm_set_state(lbm_handle h, const void *buf, size_t bytes)
         const uint8_t *wm = reinterpret_cast<const uint8_t *>(buf) + sizeof hd + popb + sizeof(uint16_t) * h->N;
         for (int n = 0; n < h->N; ++n)
             if (wm[n] > hd.n_walls) return fail(h, LBM_ERR_ARG, "state wall map names wall %d of %d", wm[n], hd.n_walls);
+        // owner codes: fluid, or a wall or sphere of the state (the kernels
+        // look solid owners up in the wall and body tables)
+        const char *op = reinterpret_cast<const char *>(buf) + sizeof hd + popb;
+        const int nsolid = hd.n_walls + hd.nb_state;
+        for (int n = 0; n < h->N; ++n) {
+            uint16_t o;
+            memcpy(&o, op + sizeof(uint16_t) * (size_t)n, sizeof o);
+            if (o != kFluid && o >= nsolid)
+                return fail(h, LBM_ERR_ARG, "state owner map names solid %d at node %d (walls + spheres = %d)", o, n,
+                            nsolid);
+        }
     }
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     const char *p = static_cast<const char *>(buf) + sizeof hd;
@@ -915,6 +1007,10 @@ lbm_status lbm_set_state(lbm_handle h, const void *buf, size_t bytes)
     h->dirty = hd.dirty != 0;
     h->steps_done = hd.steps_done;
     h->initialized = true;
+    h->geom_gen++;
+    HIP_TRY(h, launch_zero_fix(h->fsum, (int)fsum_entries(h->cfg), h->stream));
+    TRY(clear_flag(h));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
 }
 
@@ -947,11 +1043,8 @@ lbm_status lbm_profile(lbm_handle h, int32_t enable)
 {
     if (!h) return LBM_ERR_ARG;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    for (auto &p : h->prof_ev) {
-        (void)hipEventDestroy(p.first);
-        (void)hipEventDestroy(p.second);
-    }
     h->prof_ev.clear();
+    h->ev_used = 0;
     h->prof = enable != 0;
     return LBM_OK;
 }
@@ -959,18 +1052,48 @@ lbm_status lbm_profile(lbm_handle h, int32_t enable)
 lbm_status lbm_profile_read(lbm_handle h, double *ms_total, int64_t *launches)
 {
     if (!h || !ms_total || !launches) return h ? fail(h, LBM_ERR_ARG, "NULL output") : LBM_ERR_ARG;
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
-    double tot = 0.0;
-    for (auto &p : h->prof_ev) {
-        float ms = 0.f;
-        HIP_TRY(h, hipEventElapsedTime(&ms, p.first, p.second));
-        tot += ms;
-    }
-    *ms_total = tot;
-    *launches = (int64_t)h->prof_ev.size();
+    double parts[LBM_PROF_PARTS];
+    int64_t steps = 0;
+    TRY(lbm_profile_read_parts(h, parts, &steps));
+    *ms_total = parts[LBM_PROF_STEP];
+    *launches = steps;
     return LBM_OK;
 }
 
+lbm_status lbm_profile_read_parts(lbm_handle h, double *ms, int64_t *steps)
+{
+    if (!h || !ms || !steps) return h ? fail(h, LBM_ERR_ARG, "NULL output") : LBM_ERR_ARG;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    double tot[LBM_PROF_PARTS] = {0.0};
+    for (const auto &e : h->prof_ev) {
+        // parts: geometry, link pass, step kernel, forces, then the whole step
+        const int from[LBM_PROF_PARTS] = {0, 1, 2, 3, 0}, to[LBM_PROF_PARTS] = {1, 2, 3, 4, 4};
+        for (int p = 0; p < LBM_PROF_PARTS; ++p) {
+            if (e[from[p]] == e[to[p]]) continue;
+            float v = 0.f;
+            HIP_TRY(h, hipEventElapsedTime(&v, e[from[p]], e[to[p]]));
+            tot[p] += v;
+        }
+    }
+    for (int p = 0; p < LBM_PROF_PARTS; ++p) ms[p] = tot[p];
+    *steps = (int64_t)h->prof_ev.size();
+    return LBM_OK;
+}
+
+lbm_status lbm_set_step_path(lbm_handle h, int32_t path)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (path != LBM_PATH_FUSED && path != LBM_PATH_SPLIT) return fail(h, LBM_ERR_ARG, "unknown step path %d", path);
+    h->path = path;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_step_path(lbm_handle h, int32_t *path)
+{
+    if (!h || !path) return h ? fail(h, LBM_ERR_ARG, "NULL output") : LBM_ERR_ARG;
+    *path = h->path;
+    return LBM_OK;
+}
 
 lbm_status lbm_set_zieb(lbm_handle h, int32_t z_s, double area, double volume, double v_piston)
 {
@@ -1015,6 +1138,7 @@ lbm_status lbm_set_body_force(lbm_handle h, const double *F)
     if (!h || !F) return h ? fail(h, LBM_ERR_ARG, "NULL force") : LBM_ERR_ARG;
     if (!finite_all(F, 3)) return fail(h, LBM_ERR_ARG, "non-finite body force");
     for (int a = 0; a < 3; ++a) h->cfg.body_force[a] = F[a];
+    h->geom_gen++;
     return LBM_OK;
 }
 
@@ -1061,17 +1185,20 @@ lbm_status lbm_drag_gradient(lbm_handle h, int32_t nsteps, int32_t ckpt, double 
             return fail(h, LBM_ERR_OOM, "no device memory for %d checkpoints and %d recomputed states", nck, nseg);
         }
     const lbm_config &c = h->cfg;
-    // forward, keeping every ckpt-th state
+    // forward, keeping every ckpt-th state: the steps of lbm_step, so that the
+    // state and forces left behind are those of plain stepping
+    const bool prof = h->prof;
+    h->prof = false;
     for (int n = 0; n < nsteps; ++n) {
         if (n % ckpt == 0) HIP_TRY(h, hipMemcpyAsync(ck[(size_t)(n / ckpt)], h->pop[h->cur], popb, hipMemcpyDeviceToDevice, h->stream));
-        LinkArgs la = link_args(h);
-        HIP_TRY(h, launch_links(c.storage, la, h->stream));
-        StepArgs a = step_args(h);
-        a.flag = nullptr;
-        HIP_TRY(h, launch_step(c.storage, a, h->stream));
-        h->cur = 1 - h->cur;
-        h->steps_done++;
+        const lbm_status sst = step_once(h);
+        if (sst != LBM_OK) {
+            h->prof = prof;
+            release();
+            return sst;
+        }
     }
+    h->prof = prof;
     std::vector<double> acc_h((size_t)6 * nbt);
     TRY(copy_sync(h, acc_h.data(), h->acc, sizeof(double) * 6 * nbt, hipMemcpyDeviceToHost));
     double Jv = 0.0;
@@ -1171,18 +1298,23 @@ lbm_status lbm_autotune_tile(lbm_handle h, int32_t trial_steps, const char *cach
         }
     }
     // The step kernel reads the current state and writes only the spare
-    // buffer, so repeated launches leave the state as it is.
+    // buffer (and, on the fused path, the force sums, cleared afterwards), so
+    // repeated launches leave the state as it is.
     EventPair ev;
     HIP_TRY(h, ev.create());
     int best = h->tile;
     double best_us = 1e300;
+    const bool fused = h->path == LBM_PATH_FUSED;
     for (int k = 0; k < kNumTileShapes; ++k) {
         set_tile_shape(h, k);
-        StepArgs a = step_args(h);
-        a.flag = nullptr;
-        HIP_TRY(h, launch_step(h->cfg.storage, a, h->stream));
+        FusedArgs f = fused_args(h);
+        f.s.flag = nullptr;
+        auto launch = [&]() {
+            return fused ? launch_fused(h->cfg.storage, f, h->stream) : launch_step(h->cfg.storage, f.s, h->stream);
+        };
+        HIP_TRY(h, launch());
         HIP_TRY(h, hipEventRecord(ev.e0, h->stream));
-        for (int i = 0; i < trial_steps; ++i) HIP_TRY(h, launch_step(h->cfg.storage, a, h->stream));
+        for (int i = 0; i < trial_steps; ++i) HIP_TRY(h, launch());
         HIP_TRY(h, hipEventRecord(ev.e1, h->stream));
         HIP_TRY(h, hipEventSynchronize(ev.e1));
         float ms = 0.f;
@@ -1195,6 +1327,8 @@ lbm_status lbm_autotune_tile(lbm_handle h, int32_t trial_steps, const char *cach
         }
     }
     set_tile_shape(h, best);
+    HIP_TRY(h, launch_zero_fix(h->fsum, (int)fsum_entries(h->cfg), h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
     if (shape_out) *shape_out = best;
     if (cache_path) {
         cache[key] = best;
@@ -1207,6 +1341,7 @@ lbm_status lbm_autotune_tile(lbm_handle h, int32_t trial_steps, const char *cach
 
 struct lbm_batch_ctx {
     std::vector<lbm_ctx *> m;
+    std::vector<uint64_t> gen;     // members' geometry generations when the batch was built
     int storage = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -1214,15 +1349,17 @@ struct lbm_batch_ctx {
     int *d_cur = nullptr;
     int *h_cur = nullptr;          // pinned
     BatchStepArgs bs{};
-    BatchLinkArgs bl{};
     int shape = kTile64x2x2;       // tile shape of the batched step kernel
     int grid_step = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // captured graphs: one step, and a block of kBatchBlock steps
+    hipGraph_t graph1 = nullptr, graphB = nullptr;
+    hipGraphExec_t exec1 = nullptr, execB = nullptr;
     std::string err;
 };
 
 namespace {
+
+constexpr int kBatchBlock = 50;    // steps per replay of the block graph
 
 lbm_status bfail(lbm_batch_ctx *b, lbm_status st, const char *fmt, ...)
 {
@@ -1243,13 +1380,12 @@ lbm_status bfail(lbm_batch_ctx *b, lbm_status st, const char *fmt, ...)
                          hipGetErrorString(e_));                                                 \
     } while (0)
 
-// Queue one batched step: link pass and wall totals of every member, the
-// persistent step kernel over every member's tiles, and the parity flip.
+// Queue one batched step: the fused step of every member as one persistent
+// launch over their tiles, the forces of every member, and the parity flip.
 lbm_status batch_enqueue(lbm_batch_ctx *b)
 {
-    BHIP_TRY(b, launch_batch_links(b->storage, b->bl, b->stream));
-    BHIP_TRY(b, launch_batch_wall_forces(b->bl, b->stream));
     BHIP_TRY(b, launch_batch_step(b->storage, b->shape, b->bs, b->grid_step, b->stream));
+    BHIP_TRY(b, launch_batch_finish(b->bs, b->stream));
     BHIP_TRY(b, launch_batch_flip(b->d_cur, (int)b->m.size(), b->stream));
     return LBM_OK;
 }
@@ -1257,61 +1393,26 @@ lbm_status batch_enqueue(lbm_batch_ctx *b)
 void batch_release(lbm_batch_ctx *b)
 {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipGraphExec_t *e : {&b->exec1, &b->execB})
+        if (*e) {
+            (void)hipGraphExecDestroy(*e);
+            *e = nullptr;
+        }
+    for (hipGraph_t *g : {&b->graph1, &b->graphB})
+        if (*g) {
+            (void)hipGraphDestroy(*g);
+            *g = nullptr;
+        }
     if (b->d_members) (void)hipFree(b->d_members);
-    b->exec = nullptr;
-    b->graph = nullptr;
     b->d_members = nullptr;
 }
 
-// Member tables for the batch's tile shape, the step kernel's persistent
-// grid size, and the captured graph of one step.
-lbm_status batch_build(lbm_batch_ctx *b)
+// Capture `steps` batched steps into a graph and instantiate it.
+lbm_status batch_capture(lbm_batch_ctx *b, int steps, hipGraph_t *graph, hipGraphExec_t *exec)
 {
-    batch_release(b);
-    const int n = (int)b->m.size();
-    const int TX = kTileDims[b->shape][0], TY = kTileDims[b->shape][1], TZ = kTileDims[b->shape][2];
-    std::vector<BatchMember> hm((size_t)n);
-    int tiles = 0, items = 0, walls = 0;
-    for (int i = 0; i < n; ++i) {
-        lbm_ctx *h = b->m[(size_t)i];
-        BatchMember &bm = hm[(size_t)i];
-        bm.step = step_args(h);
-        bm.step.flag = nullptr;
-        bm.step.tile = b->shape;
-        bm.step.ntx = (h->cfg.nx + TX - 1) / TX;
-        bm.step.nty = (h->cfg.ny + TY - 1) / TY;
-        bm.step.ntz = (h->cfg.nz + TZ - 1) / TZ;
-        bm.step.n_tiles = bm.step.ntx * bm.step.nty * bm.step.ntz;
-        bm.links = link_args(h);
-        bm.pop[0] = h->pop[0];
-        bm.pop[1] = h->pop[1];
-        bm.tile_begin = tiles;
-        bm.item_begin = items;
-        bm.wall_begin = walls;
-        tiles += bm.step.n_tiles;
-        items += bm.links.nb + bm.links.n_wblk;
-        walls += h->n_walls;
-    }
-    BHIP_TRY(b, hipMalloc((void **)&b->d_members, sizeof(BatchMember) * (size_t)n));
-    if (!b->d_cur) BHIP_TRY(b, hipMalloc((void **)&b->d_cur, sizeof(int) * (size_t)n));
-    if (!b->h_cur) BHIP_TRY(b, hipHostMalloc((void **)&b->h_cur, sizeof(int) * (size_t)n));
-    BHIP_TRY(b, hipMemcpyAsync(b->d_members, hm.data(), sizeof(BatchMember) * (size_t)n, hipMemcpyHostToDevice,
-                               b->stream));
-    BHIP_TRY(b, hipStreamSynchronize(b->stream));
-    b->bs = BatchStepArgs{b->d_members, b->d_cur, n, tiles};
-    b->bl = BatchLinkArgs{b->d_members, b->d_cur, n, items, walls};
-    int dev = 0, cus = 0;
-    BHIP_TRY(b, hipGetDevice(&dev));
-    BHIP_TRY(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    // the persistent step kernel: as many workgroups as are resident at once,
-    // a whole number per XCD (the link kernel takes one workgroup per item)
-    const int rs = batch_step_blocks_per_cu(b->storage, b->shape);
-    b->grid_step = std::max(8, std::min(cus * rs / 8 * 8, (tiles + 7) / 8 * 8));
-    // capture one step in a graph, replayed once per step
     BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    const lbm_status st = batch_enqueue(b);
+    lbm_status st = LBM_OK;
+    for (int k = 0; k < steps && st == LBM_OK; ++k) st = batch_enqueue(b);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(b->stream, &g);
     if (st != LBM_OK) {
@@ -1319,9 +1420,58 @@ lbm_status batch_build(lbm_batch_ctx *b)
         return st;
     }
     BHIP_TRY(b, ec);
-    b->graph = g;
-    BHIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    *graph = g;
+    BHIP_TRY(b, hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
     return LBM_OK;
+}
+
+// Member tables for the batch's tile shape, the step kernel's persistent
+// grid size, and the captured graphs.
+lbm_status batch_build(lbm_batch_ctx *b)
+{
+    batch_release(b);
+    const int n = (int)b->m.size();
+    const int TX = kTileDims[b->shape][0], TY = kTileDims[b->shape][1], TZ = kTileDims[b->shape][2];
+    std::vector<BatchMember> hm((size_t)n);
+    b->gen.assign((size_t)n, 0);
+    int tiles = 0, forces = 0;
+    for (int i = 0; i < n; ++i) {
+        lbm_ctx *h = b->m[(size_t)i];
+        BatchMember &bm = hm[(size_t)i];
+        bm.f = fused_args(h);
+        StepArgs &st = bm.f.s;
+        st.flag = nullptr;
+        st.tile = b->shape;
+        st.ntx = (h->cfg.nx + TX - 1) / TX;
+        st.nty = (h->cfg.ny + TY - 1) / TY;
+        st.ntz = (h->cfg.nz + TZ - 1) / TZ;
+        st.n_tiles = st.ntx * st.nty * st.ntz;
+        bm.fin = finish_args(h);
+        bm.pop[0] = h->pop[0];
+        bm.pop[1] = h->pop[1];
+        bm.tile_begin = tiles;
+        bm.force_begin = forces;
+        tiles += st.n_tiles;
+        forces += 6 * (h->nb_state + h->n_walls);
+        b->gen[(size_t)i] = h->geom_gen;
+    }
+    BHIP_TRY(b, hipMalloc((void **)&b->d_members, sizeof(BatchMember) * (size_t)n));
+    if (!b->d_cur) BHIP_TRY(b, hipMalloc((void **)&b->d_cur, sizeof(int) * (size_t)n));
+    if (!b->h_cur) BHIP_TRY(b, hipHostMalloc((void **)&b->h_cur, sizeof(int) * (size_t)n));
+    BHIP_TRY(b, hipMemcpyAsync(b->d_members, hm.data(), sizeof(BatchMember) * (size_t)n, hipMemcpyHostToDevice,
+                               b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    b->bs = BatchStepArgs{b->d_members, b->d_cur, n, tiles, forces};
+    int dev = 0, cus = 0;
+    BHIP_TRY(b, hipGetDevice(&dev));
+    BHIP_TRY(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    // the persistent step kernel: as many workgroups as are resident at once,
+    // a whole number per XCD
+    const int rs = batch_step_blocks_per_cu(b->storage, b->shape);
+    b->grid_step = std::max(8, std::min(cus * rs / 8 * 8, (tiles + 7) / 8 * 8));
+    lbm_status st = batch_capture(b, 1, &b->graph1, &b->exec1);
+    if (st == LBM_OK) st = batch_capture(b, kBatchBlock, &b->graphB, &b->execB);
+    return st;
 }
 
 }  // namespace
@@ -1390,17 +1540,30 @@ lbm_status lbm_batch_create(const lbm_handle *members, int32_t n, void *stream, 
 
 namespace {
 
-// Wait for the members' queued work and load their state parities.
+// Wait for the members' queued work and load their state parities.  A
+// member whose geometry or state was replaced since the batch was built
+// (bodies set, stepped, state restored) is refused: the captured graphs hold
+// its old tables.
 lbm_status batch_sync_members(lbm_batch_ctx *b)
 {
     const int n = (int)b->m.size();
     for (int i = 0; i < n; ++i) {
         lbm_ctx *h = b->m[(size_t)i];
         if (h->dirty) return bfail(b, LBM_ERR_STATE, "member %d: bodies set since the batch was built", i);
+        if (h->geom_gen != b->gen[(size_t)i])
+            return bfail(b, LBM_ERR_STATE, "member %d: geometry or state replaced since the batch was built", i);
         BHIP_TRY(b, hipStreamSynchronize(h->stream));
         b->h_cur[i] = h->cur;
     }
     BHIP_TRY(b, hipMemcpyAsync(b->d_cur, b->h_cur, sizeof(int) * (size_t)n, hipMemcpyHostToDevice, b->stream));
+    return LBM_OK;
+}
+
+// Clear the members' force sums (after launches that only time the kernel).
+lbm_status batch_zero_sums(lbm_batch_ctx *b)
+{
+    for (lbm_ctx *h : b->m) BHIP_TRY(b, launch_zero_fix(h->fsum, (int)fsum_entries(h->cfg), b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
     return LBM_OK;
 }
 
@@ -1432,7 +1595,8 @@ lbm_status lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t *shape_o
     lbm_status st = batch_sync_members(b);
     if (st != LBM_OK) return st;
     // the batched step kernel reads every member's current state and writes
-    // only the spare buffers: repeated launches leave the states as they are
+    // only the spare buffers and the force sums (cleared afterwards):
+    // repeated launches leave the states as they are
     EventPair ev;
     BHIP_TRY(b, ev.create());
     int best = b->shape;
@@ -1455,6 +1619,7 @@ lbm_status lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t *shape_o
             best = k;
         }
     }
+    if ((st = batch_zero_sums(b)) != LBM_OK) return st;
     b->shape = best;
     if (shape_out) *shape_out = best;
     return batch_build(b);
@@ -1466,7 +1631,8 @@ lbm_status lbm_batch_step(lbm_batch b, int32_t nsteps)
     if (nsteps < 0) return bfail(b, LBM_ERR_ARG, "nsteps < 0");
     lbm_status st = batch_sync_members(b);
     if (st != LBM_OK) return st;
-    for (int s = 0; s < nsteps; ++s) BHIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
+    for (int s = 0; s + kBatchBlock <= nsteps; s += kBatchBlock) BHIP_TRY(b, hipGraphLaunch(b->execB, b->stream));
+    for (int s = 0; s < nsteps % kBatchBlock; ++s) BHIP_TRY(b, hipGraphLaunch(b->exec1, b->stream));
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     for (lbm_ctx *h : b->m) {
         h->cur ^= nsteps & 1;

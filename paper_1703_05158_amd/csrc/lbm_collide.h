@@ -1,0 +1,135 @@
+// Per-node collision of the D3Q19 step on gfx950, shared by the pull-collide
+// kernel and the fused step kernel: moments (eqs. dens, momentum, with the
+// Guo half-force velocity shift), the Smagorinsky relaxation time of
+// Sec. 2.2, BGK collision with the Guo source (eq. Collision_step) and the
+// store; and the inflow plane of Sec. 2.6 on the streamed populations.
+#pragma once
+
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace dev {
+
+// Inflow plane of a virtual cylinder (Sec. 2.6), on the streamed deviations
+// g of a plane node: the directions from the removed domain (c_z = +1) were
+// not received and keep the node's own values; with rho* the node's density,
+// f_12 becomes rho - (rho* - f_12) for the cylinder density rho of this step
+// (eq. ZIEBdesity9), u = sum f c / rho, and all populations are set to the
+// equilibrium at (rho, u).  The collision then follows as at every node.
+template <int S>
+__device__ __forceinline__ void zieb_plane(const StepArgs &a, const typename Store<S>::T *src, uint32_t idx,
+                                           float (&g)[kQ])
+{
+    using St = Store<S>;
+    const size_t Ns = (size_t)a.Ns;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i)
+        if (CZ[i] == 1) g[i] = St::ld(at(src + (size_t)i * Ns, idx));
+    const float rho = (float)a.zieb_state[0];
+    float rd = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) rd += g[i];
+    g[12] += rho - (a.rho0 + rd);  // deviations: f_12 - w_12 rho0 shifts by rho - rho*
+    float jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+        jx += CX[i] * g[i];
+        jy += CY[i] * g[i];
+        jz += CZ[i] * g[i];
+    }
+    const float ir = 1.0f / rho;
+    const float ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    const float uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const float w = (float)wgt(i);
+        const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+        g[i] = w * (rho - a.rho0) + w * rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+    }
+}
+
+// Collide the streamed deviations g of node idx and store the result into
+// dst.  Every lane of the wavefront stores (a solid lane stores zeros): a
+// store with lanes switched off writes partial 128-byte lines, which cost a
+// read-modify-write in HBM.  `fluid` selects the lanes whose values count.
+template <int S>
+__device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g)[kQ], bool fluid, uint32_t idx,
+                                              typename Store<S>::T *__restrict__ dst)
+{
+    using St = Store<S>;
+    const size_t Ns = (size_t)a.Ns;
+    // moments in opposite pairs (i, i+9): even and odd parts
+    float pe[10], po[10];
+#pragma unroll
+    for (int i = 1; i <= 9; ++i) {
+        pe[i] = g[i] + g[i + 9];
+        po[i] = g[i] - g[i + 9];
+    }
+    float rd = g[0], jx = 0.f, jy = 0.f, jz = 0.f;
+    float sxx = 0.f, syy = 0.f, szz = 0.f, sxy = 0.f, sxz = 0.f, syz = 0.f;
+#pragma unroll
+    for (int i = 1; i <= 9; ++i) {
+        rd += pe[i];
+        if (CX[i]) jx += CX[i] * po[i];
+        if (CY[i]) jy += CY[i] * po[i];
+        if (CZ[i]) jz += CZ[i] * po[i];
+        if (CX[i]) sxx += pe[i];
+        if (CY[i]) syy += pe[i];
+        if (CZ[i]) szz += pe[i];
+        if (CX[i] * CY[i]) sxy += CX[i] * CY[i] * pe[i];
+        if (CX[i] * CZ[i]) sxz += CX[i] * CZ[i] * pe[i];
+        if (CY[i] * CZ[i]) syz += CY[i] * CZ[i] * pe[i];
+    }
+    const float rho = a.rho0 + rd;
+    const float ir = __builtin_amdgcn_rcpf(rho);
+    const float ux = (jx + 0.5f * a.fx) * ir;
+    const float uy = (jy + 0.5f * a.fy) * ir;
+    const float uz = (jz + 0.5f * a.fz) * ir;
+    // second moment of f - feq
+    const float third = 1.0f / 3.0f;
+    const float pxx = sxx - rd * third - rho * ux * ux;
+    const float pyy = syy - rd * third - rho * uy * uy;
+    const float pzz = szz - rd * third - rho * uz * uz;
+    const float pxy = sxy - rho * ux * uy;
+    const float pxz = sxz - rho * ux * uz;
+    const float pyz = syz - rho * uy * uz;
+    float tau;
+    if (S == 0) {
+        const float Qn = pxx * pxx + pyy * pyy + pzz * pzz + 2.0f * (pxy * pxy + pxz * pxz + pyz * pyz);
+        tau = 0.5f * (a.tau0 + __builtin_sqrtf(a.tau0 * a.tau0 + a.smag_k * __builtin_sqrtf(Qn) * ir));
+    } else {
+        // 16-bit storage: the strain-rate norm and tau* in FP64
+        const double Qn = (double)pxx * pxx + (double)pyy * pyy + (double)pzz * pzz +
+                          2.0 * ((double)pxy * pxy + (double)pxz * pxz + (double)pyz * pyz);
+        const double t0 = (double)a.tau0;
+        tau = (float)(0.5 * (t0 + sqrt(t0 * t0 + (double)a.smag_k * sqrt(Qn) / (double)rho)));
+    }
+    const float om = __builtin_amdgcn_rcpf(tau);
+    const float om1 = 1.0f - om;
+    const float cf = 1.0f - 0.5f * om;
+    const float uu = ux * ux + uy * uy + uz * uz;
+    const float uF = ux * a.fx + uy * a.fy + uz * a.fz;
+    if (a.flag && fluid && !(rho > 0.f && isfinite(uu))) atomicOr(a.flag, 1);
+    {   // rest population: equilibrium deviation w0 (rd - 1.5 rho uu), source -3 w0 cf uF
+        const float w = (float)wgt(0);
+        const float v = om1 * g[0] + om * w * (rd - 1.5f * rho * uu) - 3.0f * w * cf * uF;
+        St::stnt(at(dst, idx), fluid ? v : 0.0f);
+    }
+#pragma unroll
+    for (int i = 1; i <= 9; ++i) {
+        const float w = (float)wgt(i);
+        const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+        const float cF = CX[i] * a.fx + CY[i] * a.fy + CZ[i] * a.fz;
+        // equilibrium deviation: even w (rd + rho (4.5 cu^2 - 1.5 uu)), odd 3 w rho cu
+        // Guo source: even w cf (9 cu cF - 3 uF), odd 3 w cf cF
+        const float ev = om * w * (rd + rho * (4.5f * cu * cu - 1.5f * uu)) + w * cf * (9.0f * cu * cF - 3.0f * uF);
+        const float od = 3.0f * w * (om * rho * cu + cf * cF);
+        const float vp = om1 * g[i] + ev + od, vm = om1 * g[i + 9] + ev - od;
+        St::stnt(at(dst + (size_t)i * Ns, idx), fluid ? vp : 0.0f);
+        St::stnt(at(dst + (size_t)(i + 9) * Ns, idx), fluid ? vm : 0.0f);
+    }
+}
+
+}  // namespace dev
+}  // namespace lbm

@@ -1,15 +1,15 @@
 // Owner-map maintenance and state import/export kernels (gfx950).
 //
-// The owner map is kept incrementally when spheres move: vacate the nodes a
-// sphere owned in the previous geometry and no longer covers (tagging them
-// kVacated | id), stamp the new spheres with an atomic minimum (walls and
-// lower sphere indices win; nodes a sphere keeps need no atomic), then
-// settle every old sphere's box: a node still tagged kVacated | id was
-// uncovered and is refilled with the equilibrium at rho0 and the velocity it
-// had as a solid (the solid-side Maxwell equilibrium of Sec. 2.3).  One
-// workgroup per sphere walks the sphere's bounding box: vacate and settle
-// with an 8x8x4 thread block, stamp in chunks whose owner codes each thread
-// loads together.
+// The owner map is kept incrementally when spheres move.  Vacate: every node
+// a sphere owned in the previous geometry and no longer covers is refilled
+// with the equilibrium at rho0 and the velocity it had as a solid (the
+// solid-side Maxwell equilibrium of Sec. 2.3) and marked fluid.  Stamp: the
+// new spheres take their nodes with an atomic minimum (walls and lower
+// sphere indices win; nodes a sphere keeps need no atomic).  A node vacated
+// by one sphere and stamped by another is refilled for nothing: a solid
+// node's populations are never read.  One workgroup per sphere walks the
+// sphere's bounding box: vacate with an 8x8x4 thread block, stamp in chunks
+// whose owner codes each thread loads together.
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -23,29 +23,11 @@ namespace {
 
 using namespace dev;
 
-// Visit every node of a body's box with a (8, 8, 4) workgroup.
-template <typename F>
-__device__ __forceinline__ void for_box(const Box &bx, int nx, int ny, int nz, F &&f)
-{
-    for (int kz = threadIdx.z; kz < bx.ez; kz += 4) {
-        const int pz = wrap1(bx.z0 + kz, nz);
-        for (int ky = threadIdx.y; ky < bx.ey; ky += 8) {
-            const int py = wrap1(bx.y0 + ky, ny);
-            for (int kx = threadIdx.x; kx < bx.ex; kx += 8) {
-                const int px = wrap1(bx.x0 + kx, nx);
-                f(px, py, pz, px + nx * (py + ny * pz));
-            }
-        }
-    }
-}
-
-// Offset of box coordinate v from centre coordinate c in FP32, folded to
-// the nearest periodic image.
-__device__ __forceinline__ float foff(int v, double c, int n)
-{
-    const float d = (float)((double)v - c);
-    return d > 0.5f * (float)n ? d - (float)n : (d < -0.5f * (float)n ? d + (float)n : d);
-}
+// Offset of box coordinate v from centre coordinate c, folded to the
+// nearest periodic image in FP64 and then rounded once to FP32, so that its
+// rounding error is relative to the folded offset (at most half an FP32 ulp
+// of the ball's radius plus one), not to the box size.
+__device__ __forceinline__ float foff(int v, double c, int n) { return (float)min_image((double)v - c, n); }
 
 // The nodes of old ball B's box with the (8, 8, 4) workgroup, skipping those
 // surely outside B and, when keeps, those surely inside the new ball Bn:
@@ -152,9 +134,15 @@ __global__ __launch_bounds__(kBlock) void k_walls_init(const uint8_t *wall, uint
     if (n < N) own[n] = wall[n] ? (uint16_t)(wall[n] - 1) : kFluid;
 }
 
-// Old sphere blockIdx.x against its new position (g.bodies2, g.nb2 spheres).
+// Old sphere blockIdx.x against its new position (g.bodies2, g.nb2
+// spheres): the nodes it owned and no longer covers take the equilibrium at
+// rho0 and the velocity they had as solids, in the current population
+// buffer, and become fluid (stamp may take them again for another sphere).
+template <int S>
 __global__ __launch_bounds__(kBlock) void k_vacate(GeomArgs g)
 {
+    using St = Store<S>;
+    typename St::T *pop = static_cast<typename St::T *>(g.pop);
     const int b = blockIdx.x;
     const double *B = g.bodies + b * kBodyStride;
     if (!body_ok(B, g.nx, g.ny, g.nz)) return;
@@ -166,7 +154,11 @@ __global__ __launch_bounds__(kBlock) void k_vacate(GeomArgs g)
     // a node the sphere owns lies inside its old ball; one surely inside the
     // new ball stays owned
     walk_leaving(B, Bn, keeps, nx, ny, nz, [&](int px, int py, int pz, int n) {
-        if (own[n] == id && !(keeps && inside(Bn, px, py, pz, nx, ny, nz))) own[n] = (uint16_t)(kVacated | id);
+        if (own[n] != id || (keeps && inside(Bn, px, py, pz, nx, ny, nz))) return;
+        double u0, u1, u2;
+        sphere_velocity(B, px, py, pz, nx, ny, nz, u0, u1, u2);
+        for (int i = 0; i < kQ; ++i) St::st(pop + (size_t)i * g.Ns + n, (float)eq_dev(i, g.rho0, u0, u1, u2));
+        own[n] = kFluid;
     });
 }
 
@@ -185,27 +177,6 @@ __global__ __launch_bounds__(kBlock) void k_stamp(GeomArgs g)
         [&](const BoxNode &v, uint16_t o) {
             if (o > id) atomic_min_u16(own + v.n, id);
         });
-}
-
-// Refill the nodes the old sphere `blockIdx.x` uncovered: the equilibrium at
-// rho0 and the velocity the node had as a solid; they become fluid.
-template <int S>
-__global__ __launch_bounds__(kBlock) void k_settle(GeomArgs g)
-{
-    using St = Store<S>;
-    typename St::T *pop = static_cast<typename St::T *>(g.pop);
-    const double *B = g.bodies + blockIdx.x * kBodyStride;
-    if (!body_ok(B, g.nx, g.ny, g.nz)) return;
-    const uint16_t tag = (uint16_t)(kVacated | (g.n_walls + blockIdx.x));
-    uint16_t *own = g.own;
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
-    for_box(body_box(B, 0), nx, ny, nz, [&](int px, int py, int pz, int n) {
-        if (own[n] != tag) return;
-        double u0, u1, u2;
-        sphere_velocity(B, px, py, pz, nx, ny, nz, u0, u1, u2);
-        for (int i = 0; i < kQ; ++i) St::st(pop + (size_t)i * g.Ns + n, (float)eq_dev(i, g.rho0, u0, u1, u2));
-        own[n] = kFluid;
-    });
 }
 
 template <int S>
@@ -342,7 +313,7 @@ hipError_t dispatch(int storage, dim3 grid, dim3 block, hipStream_t s, A... args
     return hipGetLastError();
 }
 
-template <int S> struct SettleK { static constexpr auto fn = k_settle<S>; };
+template <int S> struct VacateK { static constexpr auto fn = k_vacate<S>; };
 template <int S> struct InitK { static constexpr auto fn = k_init_pop<S>; };
 template <int S> struct ExportK { static constexpr auto fn = k_export_pop<S>; };
 template <int S> struct ImportK { static constexpr auto fn = k_import_pop<S>; };
@@ -356,11 +327,10 @@ hipError_t launch_walls_init(const uint8_t *wall, uint16_t *own, int N, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_vacate(const GeomArgs &g, hipStream_t s)
+hipError_t launch_vacate(int storage, const GeomArgs &g, hipStream_t s)
 {
     if (g.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_vacate, dim3(g.nb), kBoxBlock, 0, s, g);
-    return hipGetLastError();
+    return dispatch<VacateK>(storage, dim3(g.nb), kBoxBlock, s, g);
 }
 
 hipError_t launch_stamp(const GeomArgs &g, hipStream_t s)
@@ -370,11 +340,6 @@ hipError_t launch_stamp(const GeomArgs &g, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_settle(int storage, const GeomArgs &g, hipStream_t s)
-{
-    if (g.nb <= 0) return hipSuccess;
-    return dispatch<SettleK>(storage, dim3(g.nb), kBoxBlock, s, g);
-}
 
 hipError_t launch_init_pop(int storage, const GeomArgs &g, const double *rho, const double *u, hipStream_t s)
 {

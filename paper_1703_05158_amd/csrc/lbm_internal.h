@@ -11,9 +11,8 @@ namespace lbm {
 constexpr int kQ = 19;
 
 // Owner map codes (uint16 per node).  Solid owners are ids below kVacated:
-// walls 0..n_walls-1, then spheres n_walls + b.  kVacated | id marks a node
-// that the previous geometry's sphere `id` covered while the map is being
-// rebuilt (it counts as fluid); kFluid marks the fluid nodes.
+// walls 0..n_walls-1, then spheres n_walls + b; kFluid marks the fluid
+// nodes.  Every code from kVacated up counts as fluid.
 constexpr uint16_t kFluid = 0xFFFF;
 constexpr uint16_t kVacated = 0x8000;
 constexpr int kMaxIds = 0x7FFE;
@@ -95,16 +94,44 @@ struct LinkArgs {
     const int *order;             // [nb]: the order in which spheres are taken (spatially sorted), or null
 };
 
-// One lattice of a batch: its step arguments for the batch's tile shape
-// (src/dst filled in per step from pop[cur]), its link-pass arguments (pop
-// filled in likewise) and the first global tile and link-pass item it owns.
+// Fixed-point force sums of the fused step: every link's force and torque is
+// rounded to a multiple of 2^-32 and added as a 64-bit integer, so that the
+// sums do not depend on the order of the additions.  Wall sums are spread
+// over kWallRep copies (by tile) to keep the atomics of the many tiles that
+// touch a wall off one address.
+constexpr double kFixScale = 4294967296.0;  // 2^32
+constexpr int kWallRep = 64;
+
+// The fused step: per tile, the boundary links of its fluid nodes (the Sec.
+// 2.3 value of every population pulled across a cut link, formed from the
+// current state, and the momentum exchanged on the link), then the pull,
+// collision and store of the step kernel.
+struct FusedArgs {
+    StepArgs s;                   // the step (its wall-total fields unused)
+    int n_walls, nb, halfway;
+    const double *bodies;         // [nb][kBodyStride], the current geometry
+    const double *walls;          // [n_walls][kWallStride]
+    unsigned long long *fsum;     // fixed-point sums: [max_bodies][6], then [n_walls][kWallRep][6]
+    int wall_base;                // max_bodies: first wall copy of fsum
+};
+
+// Turn the fixed-point sums into the FP64 forces of the step (spheres, then
+// walls) and clear them for the next step.
+struct FinishArgs {
+    unsigned long long *fsum;
+    int wall_base, nb, n_walls;
+    double *out;                  // [nb + n_walls][6]
+};
+
+// One lattice of a batch: its fused-step arguments for the batch's tile
+// shape (src/dst filled in per step from pop[cur]), its force finish, and
+// the first global tile and force entry it owns.
 struct BatchMember {
-    StepArgs step;
-    LinkArgs links;
+    FusedArgs f;
+    FinishArgs fin;
     void *pop[2];
     int tile_begin;               // global tile index of the member's tile 0
-    int item_begin;               // global link-pass item of the member's item 0 (spheres, then wall chunks)
-    int wall_begin;               // global wall index of the member's wall 0
+    int force_begin;              // global index of the member's first force entry (6 per body and wall)
 };
 
 struct BatchStepArgs {
@@ -112,14 +139,7 @@ struct BatchStepArgs {
     const int *cur;               // [n]: member m's state is in pop[cur[m]]
     int n;
     int total_tiles;
-};
-
-struct BatchLinkArgs {
-    const BatchMember *members;
-    const int *cur;
-    int n;
-    int total_items;
-    int total_walls;
+    int total_forces;
 };
 
 // Reverse-mode step for the gradient of the summed sphere drag (FP32
@@ -156,10 +176,12 @@ struct GeomArgs {
 // storage: 0 = fp32, 1 = fp16, 2 = bf16 deviations
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t s);
 hipError_t launch_links(int storage, const LinkArgs &a, hipStream_t s);
+hipError_t launch_fused(int storage, const FusedArgs &f, hipStream_t s);
+hipError_t launch_finish(const FinishArgs &fa, hipStream_t s);
+hipError_t launch_zero_fix(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_batch_step(int storage, int shape, const BatchStepArgs &b, int grid, hipStream_t s);
 int batch_step_blocks_per_cu(int storage, int shape);   // resident workgroups per CU of the persistent step kernel
-hipError_t launch_batch_links(int storage, const BatchLinkArgs &b, hipStream_t s);
-hipError_t launch_batch_wall_forces(const BatchLinkArgs &b, hipStream_t s);
+hipError_t launch_batch_finish(const BatchStepArgs &b, hipStream_t s);
 hipError_t launch_batch_flip(int *cur, int n, hipStream_t s);
 
 hipError_t launch_zieb_update(int storage, const ZiebArgs &z, hipStream_t s);
@@ -168,9 +190,8 @@ hipError_t launch_adj_links(const AdjLinkArgs &g, hipStream_t s);
 hipError_t launch_adj_reduce(const double *dF_tile, int n_tiles, double *dF, hipStream_t s);
 
 hipError_t launch_walls_init(const uint8_t *wall, uint16_t *own, int N, hipStream_t s);
-hipError_t launch_vacate(const GeomArgs &g, hipStream_t s);
+hipError_t launch_vacate(int storage, const GeomArgs &g, hipStream_t s);
 hipError_t launch_stamp(const GeomArgs &g, hipStream_t s);
-hipError_t launch_settle(int storage, const GeomArgs &g, hipStream_t s);
 hipError_t launch_init_pop(int storage, const GeomArgs &g, const double *rho, const double *u,
                            hipStream_t s);
 hipError_t launch_export_pop(int storage, const GeomArgs &g, const double *walls, int dir,

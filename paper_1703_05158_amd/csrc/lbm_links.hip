@@ -19,6 +19,7 @@
 //    and write per-chunk sums that the step kernel adds up per wall.
 #include "lbm_device.h"
 #include "lbm_internal.h"
+#include "lbm_linkmath.h"
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -53,12 +54,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*s_red)[6])
         }
 }
 
-// Sphere kinematics of one workgroup: centre (FP64), the rest in FP32.
-struct SphereK {
-    double X0, X1, X2;
-    float V0, V1, V2, W0, W1, W2, R2;
-};
-
 // Candidate link (p, I) from the fluid node x = p + c_I to the node p of a
 // sphere.  The geometry comes first (it needs no memory): q decides which
 // second population the interpolation uses, so a link loads the owner codes
@@ -70,8 +65,7 @@ struct LinkLoad {
     uint32_t pi;
     uint16_t op, ox, ob;
     float fk, f2;         // f2: P(x)[I] when q >= 1/2, else P(x - c_K)[K]
-    float q, mw;          // Bouzidi q and the moving-boundary term
-    double d0, d1, d2;    // x - X (minimum image)
+    LinkGeo g;            // offset from the centre, q, moving-boundary term
 };
 
 template <int S>
@@ -88,33 +82,11 @@ __device__ __forceinline__ LinkLoad link_load(const LinkArgs &a, const typename 
     const int x = wrap1(px + cx, nx), y = wrap1(py + cy, ny), z = wrap1(pz + cz, nz);
     l.pi = (uint32_t)(px + nx * (py + ny * pz));
     const uint32_t xi = (uint32_t)(x + nx * (y + ny * z));
-    // geometry: distance from the centre in FP64, rounded once; q and the
-    // wall velocity in FP32
-    l.d0 = min_image((double)x - k.X0, nx);
-    l.d1 = min_image((double)y - k.X1, ny);
-    l.d2 = min_image((double)z - k.X2, nz);
-    const float e0 = (float)l.d0, e1 = (float)l.d1, e2 = (float)l.d2;
-    if (a.halfway) {
-        l.q = 0.5f;
-    } else {
-        // smallest root in (0,1] of |d + q c_K|^2 = R^2, cancellation-free form
-        const float bb = -(e0 * cx + e1 * cy + e2 * cz);
-        const float aa = (float)(cx * cx + cy * cy + cz * cz);
-        const float cc = (e0 * e0 + e1 * e1 + e2 * e2) - k.R2;
-        const float disc = fmaxf(bb * bb - aa * cc, 0.0f);
-        l.q = fminf(fmaxf(cc / (__builtin_sqrtf(disc) - bb), 0.0f), 1.0f);
-    }
-    // wall point x_b = x + q c_K relative to the centre, and its velocity
-    const float f0 = e0 - l.q * cx, f1 = e1 - l.q * cy, f2 = e2 - l.q * cz;
-    const float u0 = k.V0 + (k.W1 * f2 - k.W2 * f1);
-    const float u1 = k.V1 + (k.W2 * f0 - k.W0 * f2);
-    const float u2 = k.V2 + (k.W0 * f1 - k.W1 * f0);
-    // moving-boundary term along the reflected direction I
-    l.mw = (float)wgt(K) * a.rho0 * (cx * u0 + cy * u1 + cz * u2);
+    l.g = link_geo(k, a.halfway != 0, a.rho0, x, y, z, nx, ny, nz, I);
     l.op = *at(a.own, l.pi);
     l.ox = *at(a.own, xi);
     l.fk = St::ld(at(pop + (size_t)K * Ns, xi));
-    if (l.q < 0.5f) {
+    if (l.g.q < 0.5f) {
         const uint32_t bi = (uint32_t)(wrap1(x + cx, nx) + nx * (wrap1(y + cy, ny) + ny * wrap1(z + cz, nz)));
         l.ob = *at(a.own, bi);
         l.f2 = St::ld(at(pop + (size_t)K * Ns, bi));
@@ -135,28 +107,12 @@ __device__ __forceinline__ void link_finish(const LinkArgs &a, typename Store<S>
     using St = Store<S>;
     if (l.op != own_b || l.ox < kVacated) return;
     const int I = l.I;
-    const int cx = dcx(I), cy = dcy(I), cz = dcz(I);  // c_I = -c_K
-    const float q = l.q;
-    float val;
-    if (q < 0.5f) {
-        val = l.ob >= kVacated ? 2.0f * q * l.fk + (1.0f - 2.0f * q) * l.f2 + 6.0f * l.mw : l.fk + 6.0f * l.mw;
-    } else {
-        const float h = 0.5f / q;
-        val = h * l.fk + (1.0f - h) * l.f2 + (3.0f / q) * l.mw;
-    }
-    const float vr = St::round(val);
+    const bool behind = l.ob >= kVacated;
+    const float vr = St::round(link_value(l.g.q, l.fk, l.f2, l.f2, behind, l.g.mw));
     St::st(at(pop + (size_t)I * (size_t)a.Ns, l.pi), vr);
-    // momentum handed to the body along c_K (full populations), arm x_b - X
-    const double mom = (double)l.fk + (double)vr + 2.0 * wgt(I) * (double)a.rho0;
-    const double qd = (double)q;
-    const double ar0 = l.d0 - qd * cx, ar1 = l.d1 - qd * cy, ar2 = l.d2 - qd * cz;
-    const double F0 = -mom * cx, F1 = -mom * cy, F2 = -mom * cz;
-    acc[0] += F0;
-    acc[1] += F1;
-    acc[2] += F2;
-    acc[3] += ar1 * F2 - ar2 * F1;
-    acc[4] += ar2 * F0 - ar0 * F2;
-    acc[5] += ar0 * F1 - ar1 * F0;
+    double a0, a1, a2;
+    sphere_arm(l.g, I, a0, a1, a2);
+    link_force(link_momentum(l.fk, vr, I, a.rho0), I, a0, a1, a2, acc);
 }
 
 constexpr int kItemCap = 4096;   // candidate links held at once
@@ -220,29 +176,6 @@ __device__ __forceinline__ float box_off(int v, double c) { return (float)((doub
 
 // Number of bits that hold 0 .. e - 1.
 __device__ __forceinline__ int field_bits(int e) { return e > 1 ? 32 - __clz(e - 1) : 1; }
-
-// Exclusive prefix of `cnt` over the workgroup and the total.
-__device__ __forceinline__ int block_scan(int cnt, int *wtot, int &tot)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int incl = cnt;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int v = __shfl_up(incl, off);
-        if (lane >= off) incl += v;
-    }
-    if (lane == 63) wtot[wv] = incl;
-    __syncthreads();
-    int pos = incl - cnt;
-    tot = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-        const int t = wtot[w];
-        if (w < wv) pos += t;
-        tot += t;
-    }
-    return pos;
-}
 
 // Exclusive prefix over the workgroup of each of the NW words (in v) and
 // their totals (in tot).
@@ -338,17 +271,7 @@ __device__ __forceinline__ void sphere_block(const LinkArgs &a, int b, SphereLds
         const Box bx = body_box(B, 0);
         const int total = bx.ex * bx.ey * bx.ez;
         const uint16_t own_b = (uint16_t)(a.n_walls + b);
-        SphereK k;
-        k.X0 = B[0];
-        k.X1 = B[1];
-        k.X2 = B[2];
-        k.V0 = (float)B[3];
-        k.V1 = (float)B[4];
-        k.V2 = (float)B[5];
-        k.W0 = (float)B[6];
-        k.W1 = (float)B[7];
-        k.W2 = (float)B[8];
-        k.R2 = (float)(B[9] * B[9]);
+        const SphereK k = sphere_k(B);
         const float mg = 0.01f + 1e-5f * k.R2;
         const float ri = (float)B[9] - 1.5f;
         const float in2 = ri > 0.0f ? ri * ri - mg : -1.0f;
@@ -458,9 +381,7 @@ __device__ __forceinline__ void wall_block(const LinkArgs &a, int blk, double (*
     const int w = seg / (kQ - 1), I = seg - (kQ - 1) * w + 1, K = opp(I);
     const int cx = dcx(I), cy = dcy(I), cz = dcz(I);  // c_I = -c_K
     const double *wl = a.walls + w * kWallStride;
-    const float wk = (float)wgt(K);
-    const float add = 6.0f * (wk * a.rho0 * (float)(cx * wl[0] + cy * wl[1] + cz * wl[2]));
-    const double w2 = 2.0 * (double)wk * (double)a.rho0;
+    const float add = wall_term(wl, I, a.rho0);
     // momentum sum and its first moment about the reference point; the
     // chunk's kWallChunk / kBlock links per thread have their loads in flight
     // together
@@ -491,7 +412,7 @@ __device__ __forceinline__ void wall_block(const LinkArgs &a, int blk, double (*
         const int sx = wrap1((int)x - cx, nx), sy = wrap1((int)y - cy, ny), sz = wrap1((int)z - cz, a.nz);
         const float vr = St::round(fk[u] + add);
         St::st(at(pop + (size_t)I * Ns, (uint32_t)(sx + nx * (sy + ny * sz))), vr);
-        const double mom = (double)fk[u] + (double)vr + w2;
+        const double mom = link_momentum(fk[u], vr, I, a.rho0);
         v[0] += mom;
         v[1] += mom * ((double)x - 0.5 * cx - wl[3]);
         v[2] += mom * ((double)y - 0.5 * cy - wl[4]);
@@ -554,11 +475,7 @@ __device__ __forceinline__ void adj_sphere_block(const AdjLinkArgs &g, int b, Sp
         const Box bx = body_box(B, 0);
         const int total = bx.ex * bx.ey * bx.ez;
         const uint16_t own_b = (uint16_t)(a.n_walls + b);
-        SphereK k;
-        k.X0 = B[0];
-        k.X1 = B[1];
-        k.X2 = B[2];
-        k.R2 = (float)(B[9] * B[9]);
+        const SphereK k = sphere_k(B);
         const float mg = 0.01f + 1e-5f * k.R2;
         const float ri = (float)B[9] - 1.5f;
         const float in2 = ri > 0.0f ? ri * ri - mg : -1.0f;
@@ -586,17 +503,7 @@ __device__ __forceinline__ void adj_sphere_block(const AdjLinkArgs &g, int b, Sp
                 const uint32_t pi = (uint32_t)(px + nx * (py + ny * pz));
                 const uint32_t xi = (uint32_t)(x + nx * (y + ny * z));
                 if (*at(a.own, pi) != own_b || *at(a.own, xi) < kVacated) continue;
-                float q = 0.5f;
-                if (!a.halfway) {
-                    const float e0 = (float)min_image((double)x - k.X0, nx);
-                    const float e1 = (float)min_image((double)y - k.X1, ny);
-                    const float e2 = (float)min_image((double)z - k.X2, nz);
-                    const float bb = -(e0 * cx + e1 * cy + e2 * cz);
-                    const float aa = (float)(cx * cx + cy * cy + cz * cz);
-                    const float cc = (e0 * e0 + e1 * e1 + e2 * e2) - k.R2;
-                    const float disc = fmaxf(bb * bb - aa * cc, 0.0f);
-                    q = fminf(fmaxf(cc / (__builtin_sqrtf(disc) - bb), 0.0f), 1.0f);
-                }
+                const float q = link_geo(k, a.halfway != 0, a.rho0, x, y, z, nx, ny, nz, I).q;
                 const float ckx = (float)(-cx);
                 const float m = g.mu ? *at(g.mu + (size_t)I * Ns, pi) : ckx;
                 float ak, ab = 0.f, ai = 0.f, aw;
@@ -639,92 +546,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_links(AdjLinkArgs g)
     adj_sphere_block(g, blockIdx.x, L, s_red);
 }
 
-// Largest m with key(m) <= g over the members of a batch.
-template <typename F>
-__device__ __forceinline__ int find_member(int n, int g, F key)
-{
-    int m = 0, top = n;
-    while (top - m > 1) {
-        const int mid = (m + top) >> 1;
-        if (key(mid) <= g) m = mid;
-        else top = mid;
-    }
-    return m;
-}
-
-// Link pass over many lattices: one workgroup per item, item j of member m
-// being sphere j (j < nb, taken in the member's sphere order) or wall chunk
-// j - nb.  Not persistent: without a loop over items the kernel fits 168
-// VGPRs, i.e. 3 waves per SIMD.
-template <int S>
-__global__ __launch_bounds__(kBlock, 3) void k_batch_links(BatchLinkArgs b)
-{
-    __shared__ SphereLds L;
-    __shared__ double s_red[kWaves][6];
-    const int g = blockIdx.x;
-    const int m = find_member(b.n, g, [&](int i) { return b.members[i].item_begin; });
-    const BatchMember &bm = b.members[m];
-    LinkArgs t = bm.links;
-    t.pop = bm.pop[b.cur[m]];
-    const LinkArgs a = uniform(t);
-    const int j = g - bm.item_begin;
-    if (j < a.nb)
-        sphere_block<S>(a, a.order ? a.order[j] : j, L, s_red);
-    else
-        wall_block<S>(a, j - a.nb, s_red);
-}
-
-// Wall totals of every member: one 64-thread workgroup per wall.
-__global__ __launch_bounds__(64) void k_batch_wall_forces(BatchLinkArgs b)
-{
-    const int g = blockIdx.x, lane = threadIdx.x;
-    const int m = find_member(b.n, g, [&](int i) { return b.members[i].wall_begin; });
-    const LinkArgs &a = b.members[m].links;
-    const int w = g - b.members[m].wall_begin;
-    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int j = a.wl_wblk[w] + lane; j < a.wl_wblk[w + 1]; j += 64)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) v[c] += a.wl_part[6 * (size_t)j + c];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) v[c] += __shfl_xor(v[c], off);
-    if (lane < 6) a.out[6 * (a.nb + w) + lane] = v[lane];
-}
-
-__global__ __launch_bounds__(kBlock) void k_batch_flip(int *cur, int n)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) cur[i] ^= 1;
-}
-
 }  // namespace
-
-hipError_t launch_batch_links(int storage, const BatchLinkArgs &b, hipStream_t s)
-{
-    if (b.total_items <= 0) return hipSuccess;
-    const int grid = b.total_items;
-    switch (storage) {
-    case 0: hipLaunchKernelGGL(k_batch_links<0>, dim3(grid), dim3(kBlock), 0, s, b); break;
-    case 1: hipLaunchKernelGGL(k_batch_links<1>, dim3(grid), dim3(kBlock), 0, s, b); break;
-    case 2: hipLaunchKernelGGL(k_batch_links<2>, dim3(grid), dim3(kBlock), 0, s, b); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_wall_forces(const BatchLinkArgs &b, hipStream_t s)
-{
-    if (b.total_walls <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_wall_forces, dim3(b.total_walls), dim3(64), 0, s, b);
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_flip(int *cur, int n, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_batch_flip, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, cur, n);
-    return hipGetLastError();
-}
 
 hipError_t launch_adj_links(const AdjLinkArgs &g, hipStream_t s)
 {

@@ -14,6 +14,7 @@
 // 128-byte lines, which cost a read-modify-write in HBM (one solid node per
 // 64-node row made the whole step a quarter slower).  The value a solid node
 // holds is never read before the link pass of the next step replaces it.
+#include "lbm_collide.h"
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -24,44 +25,6 @@ namespace lbm {
 namespace {
 
 using namespace dev;
-
-// Inflow plane of a virtual cylinder (Sec. 2.6), on the streamed deviations
-// g of a plane node: the directions from the removed domain (c_z = +1) were
-// not received and keep the node's own values; with rho* the node's density,
-// f_12 becomes rho - (rho* - f_12) for the cylinder density rho of this step
-// (eq. ZIEBdesity9), u = sum f c / rho, and all populations are set to the
-// equilibrium at (rho, u).  The collision then follows as at every node.
-template <int S>
-__device__ __forceinline__ void zieb_plane(const StepArgs &a, const typename Store<S>::T *src, uint32_t idx,
-                                        float (&g)[kQ])
-{
-    using St = Store<S>;
-    const size_t Ns = (size_t)a.Ns;
-#pragma unroll
-    for (int i = 1; i < kQ; ++i)
-        if (CZ[i] == 1) g[i] = St::ld(at(src + (size_t)i * Ns, idx));
-    const float rho = (float)a.zieb_state[0];
-    float rd = 0.0f;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) rd += g[i];
-    g[12] += rho - (a.rho0 + rd);  // deviations: f_12 - w_12 rho0 shifts by rho - rho*
-    float jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-    for (int i = 1; i < kQ; ++i) {
-        jx += CX[i] * g[i];
-        jy += CY[i] * g[i];
-        jz += CZ[i] * g[i];
-    }
-    const float ir = 1.0f / rho;
-    const float ux = jx * ir, uy = jy * ir, uz = jz * ir;
-    const float uu = ux * ux + uy * uy + uz * uz;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const float w = (float)wgt(i);
-        const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-        g[i] = w * (rho - a.rho0) + w * rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
-    }
-}
 
 // Tile t (TX x TY x TZ nodes, one per thread) of the lattice described by a.
 template <int S, int TX, int TY, int TZ>
@@ -103,78 +66,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int t)
         }
         if (z == a.zieb_z) zieb_plane<S>(a, src, idx, g);
     }
-    {
-        // moments in opposite pairs (i, i+9): even and odd parts
-        float pe[10], po[10];
-#pragma unroll
-        for (int i = 1; i <= 9; ++i) {
-            pe[i] = g[i] + g[i + 9];
-            po[i] = g[i] - g[i + 9];
-        }
-        float rd = g[0], jx = 0.f, jy = 0.f, jz = 0.f;
-        float sxx = 0.f, syy = 0.f, szz = 0.f, sxy = 0.f, sxz = 0.f, syz = 0.f;
-#pragma unroll
-        for (int i = 1; i <= 9; ++i) {
-            rd += pe[i];
-            if (CX[i]) jx += CX[i] * po[i];
-            if (CY[i]) jy += CY[i] * po[i];
-            if (CZ[i]) jz += CZ[i] * po[i];
-            if (CX[i]) sxx += pe[i];
-            if (CY[i]) syy += pe[i];
-            if (CZ[i]) szz += pe[i];
-            if (CX[i] * CY[i]) sxy += CX[i] * CY[i] * pe[i];
-            if (CX[i] * CZ[i]) sxz += CX[i] * CZ[i] * pe[i];
-            if (CY[i] * CZ[i]) syz += CY[i] * CZ[i] * pe[i];
-        }
-        const float rho = a.rho0 + rd;
-        const float ir = __builtin_amdgcn_rcpf(rho);
-        const float ux = (jx + 0.5f * a.fx) * ir;
-        const float uy = (jy + 0.5f * a.fy) * ir;
-        const float uz = (jz + 0.5f * a.fz) * ir;
-        // second moment of f - feq
-        const float third = 1.0f / 3.0f;
-        const float pxx = sxx - rd * third - rho * ux * ux;
-        const float pyy = syy - rd * third - rho * uy * uy;
-        const float pzz = szz - rd * third - rho * uz * uz;
-        const float pxy = sxy - rho * ux * uy;
-        const float pxz = sxz - rho * ux * uz;
-        const float pyz = syz - rho * uy * uz;
-        float tau;
-        if (S == 0) {
-            const float Qn = pxx * pxx + pyy * pyy + pzz * pzz + 2.0f * (pxy * pxy + pxz * pxz + pyz * pyz);
-            tau = 0.5f * (a.tau0 + __builtin_sqrtf(a.tau0 * a.tau0 + a.smag_k * __builtin_sqrtf(Qn) * ir));
-        } else {
-            // 16-bit storage: the strain-rate norm and tau* in FP64
-            const double Qn = (double)pxx * pxx + (double)pyy * pyy + (double)pzz * pzz +
-                              2.0 * ((double)pxy * pxy + (double)pxz * pxz + (double)pyz * pyz);
-            const double t0 = (double)a.tau0;
-            tau = (float)(0.5 * (t0 + sqrt(t0 * t0 + (double)a.smag_k * sqrt(Qn) / (double)rho)));
-        }
-        const float om = __builtin_amdgcn_rcpf(tau);
-        const float om1 = 1.0f - om;
-        const float cf = 1.0f - 0.5f * om;
-        const float uu = ux * ux + uy * uy + uz * uz;
-        const float uF = ux * a.fx + uy * a.fy + uz * a.fz;
-        if (a.flag && fluid && !(rho > 0.f && isfinite(uu))) atomicOr(a.flag, 1);
-        {   // rest population: equilibrium deviation w0 (rd - 1.5 rho uu), source -3 w0 cf uF
-            const float w = (float)wgt(0);
-            const float v = om1 * g[0] + om * w * (rd - 1.5f * rho * uu) - 3.0f * w * cf * uF;
-            St::stnt(at(dst, idx), fluid ? v : 0.0f);
-        }
-#pragma unroll
-        for (int i = 1; i <= 9; ++i) {
-            const float w = (float)wgt(i);
-            const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-            const float cF = CX[i] * a.fx + CY[i] * a.fy + CZ[i] * a.fz;
-            // equilibrium deviation: even w (rd + rho (4.5 cu^2 - 1.5 uu)), odd 3 w rho cu
-            // Guo source: even w cf (9 cu cF - 3 uF), odd 3 w cf cF
-            const float ev = om * w * (rd + rho * (4.5f * cu * cu - 1.5f * uu)) + w * cf * (9.0f * cu * cF - 3.0f * uF);
-            const float od = 3.0f * w * (om * rho * cu + cf * cF);
-            const float vp = om1 * g[i] + ev + od, vm = om1 * g[i + 9] + ev - od;
-            St::stnt(at(dst + (size_t)i * Ns, idx), fluid ? vp : 0.0f);
-            St::stnt(at(dst + (size_t)(i + 9) * Ns, idx), fluid ? vm : 0.0f);
-        }
-    }
+    collide_store<S>(a, g, fluid, idx, dst);
 }
 
 // Force and torque on wall w: the sum of its link-pass chunks, by the first
@@ -200,40 +92,6 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
     if (threadIdx.x < 64)
         for (int w = blockIdx.x; w < a.n_wsum; w += gridDim.x) wall_total(a, w);
     tile_step<S, TX, TY, TZ>(a, xcd_remap(blockIdx.x, gridDim.x));
-}
-
-// Persistent step over the tiles of many lattices, all with the batch's tile
-// shape.  Member m owns the global tiles [tile_begin[m], tile_begin[m + 1]);
-// XCD k (workgroups k, k + 8, ...) walks the k-th eighth of the global tile
-// range, so that each XCD works on neighbouring tiles of the same members.
-template <int S, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_batch_step(BatchStepArgs b)
-{
-    const int xcd = blockIdx.x & 7, stride = gridDim.x >> 3;
-    const int lo = (int)((long long)b.total_tiles * xcd / 8), hi = (int)((long long)b.total_tiles * (xcd + 1) / 8);
-    // the member of the previous tile is kept: a workgroup's next tile is
-    // usually in the same member
-    int mb = 0, me = 0;
-    StepArgs a{};
-    for (int g = lo + (int)(blockIdx.x >> 3); g < hi; g += stride) {
-        if (g < mb || g >= me) {
-            int m = 0, top = b.n;  // largest m with tile_begin[m] <= g
-            while (top - m > 1) {
-                const int mid = (m + top) >> 1;
-                if (b.members[mid].tile_begin <= g) m = mid;
-                else top = mid;
-            }
-            const BatchMember &bm = b.members[m];
-            mb = bm.tile_begin;
-            me = m + 1 < b.n ? b.members[m + 1].tile_begin : b.total_tiles;
-            StepArgs t = bm.step;
-            const int c = b.cur[m];
-            t.src = bm.pop[c];
-            t.dst = bm.pop[c ^ 1];
-            a = uniform(t);
-        }
-        tile_step<S, TX, TY, TZ>(a, g - mb);
-    }
 }
 
 template <int S>
@@ -529,48 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce(const double *dF_tile, in
     }
 }
 
-// The batched step kernel for a storage type and tile shape.
-template <int S>
-const void *batch_step_kernel_s(int shape)
-{
-    switch (shape) {
-    case kTile64x2x2: return (const void *)k_batch_step<S, 64, 2, 2>;
-    case kTile32x4x2: return (const void *)k_batch_step<S, 32, 4, 2>;
-    case kTile32x2x4: return (const void *)k_batch_step<S, 32, 2, 4>;
-    case kTile16x8x2: return (const void *)k_batch_step<S, 16, 8, 2>;
-    default: return nullptr;
-    }
-}
-
-const void *batch_step_kernel(int storage, int shape)
-{
-    switch (storage) {
-    case 0: return batch_step_kernel_s<0>(shape);
-    case 1: return batch_step_kernel_s<1>(shape);
-    case 2: return batch_step_kernel_s<2>(shape);
-    default: return nullptr;
-    }
-}
-
 }  // namespace
-
-int batch_step_blocks_per_cu(int storage, int shape)
-{
-    const void *k = batch_step_kernel(storage, shape);
-    int n = 0;
-    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kBlock, 0) != hipSuccess || n < 1) return 1;
-    return n;
-}
-
-hipError_t launch_batch_step(int storage, int shape, const BatchStepArgs &b, int grid, hipStream_t s)
-{
-    if (b.total_tiles <= 0) return hipSuccess;
-    const void *k = batch_step_kernel(storage, shape);
-    if (!k) return hipErrorInvalidValue;
-    BatchStepArgs arg = b;
-    void *args[] = {&arg};
-    return hipLaunchKernel(k, dim3(grid), dim3(kBlock), args, 0, s);
-}
 
 hipError_t launch_adj_collide(const AdjStepArgs &g, hipStream_t s)
 {

@@ -34,8 +34,8 @@ def test_record_traffic_scales_by_the_copy(bench, tmp_path):
     copy = "__amd_rocclr_copyBuffer"
     _csv(tmp_path / "pc_fetch", [(copy, 1, 16.0), (copy, 2, gib_kib / 2)])   # FETCH_SIZE sees half the reads
     _csv(tmp_path / "pc_write", [(copy, 1, 8.0), (copy, 2, gib_kib)])
-    step32 = "void lbm::(anonymous namespace)::k_step<0, 64, 2, 2>(lbm::StepArgs)"
-    step16 = "void lbm::(anonymous namespace)::k_step<1, 32, 4, 2>(lbm::StepArgs)"
+    step32 = "void lbm::(anonymous namespace)::k_fused<0, 64, 2, 2>(lbm::FusedArgs)"
+    step16 = "void lbm::(anonymous namespace)::k_fused<1, 32, 4, 2>(lbm::FusedArgs)"
     links = "void lbm::(anonymous namespace)::k_links<0>(lbm::LinkArgs)"
     _csv(tmp_path / "pb_fetch_f32", [(step32, 1, 100.0), (step32, 2, 300.0), (links, 3, 5.0)])
     _csv(tmp_path / "pb_write_f32", [(step32, 1, 50.0), (step32, 2, 50.0)])
@@ -43,8 +43,8 @@ def test_record_traffic_scales_by_the_copy(bench, tmp_path):
     _csv(tmp_path / "pb_write_f16", [(step16, 1, 4.0)])
     bench.record_traffic(str(tmp_path))
     rec = json.load(open(bench.TRAFFIC_FILE))
-    assert rec["f32"]["tiles"]["64x2x2"]["kernel"] == "k_step<0,64,2,2>"
-    assert rec["f16"]["tiles"]["32x4x2"]["kernel"] == "k_step<1,32,4,2>"
+    assert rec["f32"]["tiles"]["64x2x2"]["kernel"] == "k_fused<0,64,2,2>"
+    assert rec["f16"]["tiles"]["32x4x2"]["kernel"] == "k_fused<1,32,4,2>"
     assert rec["f32"]["fetch_scale"] == pytest.approx(2.0) and rec["f32"]["write_scale"] == pytest.approx(1.0)
     # mean over dispatches: fetch 200 KiB x 2, write 50 KiB x 1
     assert rec["f32"]["tiles"]["64x2x2"]["bytes_per_launch"] == 200 * 1024 * 2 + 50 * 1024
@@ -69,16 +69,16 @@ def test_record_traffic_per_tile_shape(bench, tmp_path):
     copy = "__amd_rocclr_copyBuffer"
     _csv(tmp_path / "pc_fetch", [(copy, 1, 4.0)])
     _csv(tmp_path / "pc_write", [(copy, 1, 4.0)])
-    a = "void lbm::(anonymous namespace)::k_step<0, 64, 2, 2>(lbm::StepArgs)"
-    b = "void lbm::(anonymous namespace)::k_step<0, 32, 2, 4>(lbm::StepArgs)"
-    c = "void lbm::(anonymous namespace)::k_step<0, 16, 8, 2>(lbm::StepArgs)"
+    a = "void lbm::(anonymous namespace)::k_fused<0, 64, 2, 2>(lbm::FusedArgs)"
+    b = "void lbm::(anonymous namespace)::k_fused<0, 32, 2, 4>(lbm::FusedArgs)"
+    c = "void lbm::(anonymous namespace)::k_fused<0, 16, 8, 2>(lbm::FusedArgs)"
     _csv(tmp_path / "pb_fetch_f32", [(a, 1, 1.0), (b, 2, 2.0), (c, 3, 3.0)])
     _csv(tmp_path / "pb_write_f32", [(a, 1, 1.0), (b, 2, 1.0)])
     _csv(tmp_path / "pb_fetch_f16", [])
     _csv(tmp_path / "pb_write_f16", [])
     with pytest.raises(SystemExit):
         bench.record_traffic(str(tmp_path))
-    f16 = "void lbm::(anonymous namespace)::k_step<1, 64, 2, 2>(lbm::StepArgs)"
+    f16 = "void lbm::(anonymous namespace)::k_fused<1, 64, 2, 2>(lbm::FusedArgs)"
     _csv(tmp_path / "pb_fetch_f16", [(f16, 1, 1.0)])
     _csv(tmp_path / "pb_write_f16", [(f16, 1, 1.0)])
     bench.record_traffic(str(tmp_path))

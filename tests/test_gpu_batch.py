@@ -3,7 +3,8 @@
 Every tile shape runs the same per-node arithmetic, and the batched kernels
 run the per-tile and per-sphere device code of the single-lattice kernels,
 so results must agree bit for bit; the autotuner must leave the state as it
-found it.
+found it.  Batched members are also held to the FP64 oracle at the step's
+bars (populations 1e-5 relative, forces and torques 1e-4 norm-relative).
 """
 import json
 
@@ -87,7 +88,8 @@ def test_batch_matches_single_lattices(torch_stream, storage):
     single[0].set_tile(1)
     single[3].set_tile(3)
     b = Batch(batched, stream=torch_stream)
-    for k, shape in ((7, 0), (4, 3), (1, 2), (2, 1)):
+    # 53 steps: one replay of the 50-step graph, then three of the one-step graph
+    for k, shape in ((7, 0), (4, 3), (1, 2), (2, 1), (53, 0)):
         b.set_tile(shape)
         assert b.tile == shape
         for lat in single:
@@ -144,3 +146,69 @@ def test_batch_rejects_bad_members(torch_stream):
         Batch([a])
     for lat in (a, b16, raw):
         lat.close()
+
+
+def test_batch_matches_oracle(torch_stream):
+    """Five uneven members stepped as one batch for 20 steps (one-step graph
+    replays), then 50 more (one replay of the 50-step graph), each against
+    its own FP64 oracle run: spheres with Bouzidi and halfway links, side
+    walls, a moving piston wall, an orifice plate, body forces along
+    different axes, a box with no solids."""
+    import oracle
+    from paper_1703_05158_amd import Batch, Lattice
+    from ._pair import force_rel_err, pop_rel_err
+    members = _members() + [
+        (W.case_duct(nx=40, ny=36, nz=80, n_spheres=12, orifice_z=60, orifice_r_in=9, orifice_gap=3,
+                     pack_z=(6, 50), v_sigma=0.01, w_sigma=0.002, seed=25, drift=False), "halfway"),
+    ]
+    lats, ors = [], []
+    for c, bb in members:
+        lats.append(Lattice.from_case(c, bb_mode=bb, stream=torch_stream))
+        ors.append(oracle.Oracle.from_case(c, halfway=bb == "halfway"))
+    b = Batch(lats, stream=torch_stream)
+    done = 0
+    for k in (20, 50):
+        b.step(k)
+        for o in ors:
+            o.step(k)
+        done += k
+        for (c, bb), o, lat in zip(members, ors, lats):
+            pe = pop_rel_err(o, lat)
+            fe, te = force_rel_err(o, lat)
+            print(f"{c.name} ({bb}) after {done}: pop {pe:.2e} F {fe:.2e} T {te:.2e}")
+            assert pe <= 1e-5 and fe <= 1e-4 and te <= 1e-4
+            assert lat.info()["steps_done"] == done
+    b.close()
+    for lat in lats:
+        lat.close()
+
+
+def test_batch_refuses_members_changed_after_build(torch_stream):
+    """A member whose geometry, body force or state was replaced after the
+    batch was built is refused (the captured graphs hold its old tables)."""
+    from paper_1703_05158_amd import Batch, LBMError, Lattice
+    (case, _), (case2, _) = _members()[0], _members()[2]
+    for change in ("bodies", "state", "force"):
+        a = Lattice.from_case(case, stream=torch_stream)
+        c = Lattice.from_case(case2, stream=torch_stream)
+        start = a.get_state()
+        b = Batch([a, c], stream=torch_stream)
+        b.step(2)
+        if change == "bodies":
+            X, V, Om, R = case.bodies_at(0)
+            a.set_bodies(X + 0.3, V, Om, R)
+            a.step(1)
+        elif change == "state":
+            a.set_state(start)
+        else:
+            a.set_body_force([0.0, 2e-6, 0.0])
+        with pytest.raises(LBMError) as e:
+            b.step(1)
+        assert e.value.status == 4
+        b.close()
+        # a new batch takes the changed member
+        b = Batch([a, c], stream=torch_stream)
+        b.step(1)
+        b.close()
+        a.close()
+        c.close()

@@ -254,8 +254,9 @@ def test_state_checkpoint_resume_bitwise(torch_stream, storage):
 
 def test_state_rejects_a_corrupt_header(torch_stream):
     """Checkpoint headers with body or wall counts beyond the handle's
-    capacities, or a bad flag, are rejected on the host; the handle then
-    steps on exactly as if nothing had been offered."""
+    capacities, or a bad flag, and owner maps naming solids the state does
+    not have, are rejected on the host; the handle then steps on exactly as
+    if nothing had been offered."""
     import struct
     from paper_1703_05158_amd import LBMError, Lattice
     case = W.case_box(n=(20, 18, 16), n_spheres=3, radius=(2.0, 3.0), v_sigma=0.02, seed=9, drift=True)
@@ -272,6 +273,17 @@ def test_state_rejects_a_corrupt_header(torch_stream):
         struct.pack_into("<i", bad, off, val)
         with pytest.raises(LBMError):
             lat.set_state(bytes(bad))
+    # owner codes naming a solid beyond the state's walls and spheres (the
+    # map follows the 56-byte header and the populations: 19 arrays of
+    # N rounded up to 64 plus 1088 FP32 values)
+    N = case.nx * case.ny * case.nz
+    own_at = 56 + 19 * 4 * ((N + 63) // 64 * 64 + 1088)
+    assert struct.unpack_from("<H", good, own_at + 2 * 5)[0] in (0xFFFF, 0, 1, 2)
+    for node, code in ((5, 3), (N - 1, 0x7FFD), (100, 0x8001)):
+        bad = bytearray(good)
+        struct.pack_into("<H", bad, own_at + 2 * node, code)
+        with pytest.raises(LBMError):
+            lat.set_state(bytes(bad))
     for n in range(2, 5):
         for l in (lat, ref):
             l.set_bodies(*case.bodies_at(n))
@@ -282,17 +294,24 @@ def test_state_rejects_a_corrupt_header(torch_stream):
 
 
 def test_nan_guard_reports_unstable(torch_stream):
+    """The guard reports a non-positive density, and a restored good state
+    (checkpoint or populations) steps on without the old report."""
     from paper_1703_05158_amd import LBMError, Lattice
     case = W.case_box(n=(16, 16, 16), n_spheres=0, u_sigma=0.0, seed=0)
     lat = Lattice.from_case(case, stream=torch_stream, nan_guard_every=1)
     lat.step(2)
+    good = lat.get_state()
     f = lat.get_populations()
     # negate a 3x3x3 block: its centre pulls only negated values (rho = -1)
-    f[:, 2:5, 3:6, 4:7] = -f[:, 2:5, 3:6, 4:7]
-    lat.set_populations(f)
-    with pytest.raises(LBMError) as e:
-        lat.step(1)
-    assert e.value.status == 5
+    bad = f.copy()
+    bad[:, 2:5, 3:6, 4:7] = -bad[:, 2:5, 3:6, 4:7]
+    for restore in (lambda: lat.set_state(good), lambda: lat.set_populations(f)):
+        lat.set_populations(bad)
+        with pytest.raises(LBMError) as e:
+            lat.step(1)
+        assert e.value.status == 5
+        restore()
+        lat.step(3)
     lat.close()
 
 

@@ -1,0 +1,158 @@
+"""The fused step kernel against the split path (boundary-link pass, then the
+pull-collide kernel), and the per-part event timing.
+
+Both paths form every link value with the same FP32 arithmetic, so their
+populations must agree bit for bit, with every storage type, link mode,
+moving spheres, moving walls and the inflow plane.  Their forces differ only
+in how the per-link FP64 terms are summed: each term is rounded to a
+multiple of 2^-32 on the fused path and summed exactly, and summed in FP64
+in a fixed order on the split path.  So for a body with L links each
+component differs by at most L 2^-33 plus the FP64 rounding of the split
+path's sums; the bar takes L from the owner map.  Both paths are also held
+to the oracle.
+"""
+import numpy as np
+import pytest
+
+import lbm_workloads as W
+
+from ._pair import advance, force_rel_err, make_pair, pop_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _both(case, stream, storage="f32", bb_mode="bouzidi", steps=12, max_bodies=None):
+    from paper_1703_05158_amd import Lattice
+    lats = [Lattice.from_case(case, storage=storage, bb_mode=bb_mode, stream=stream, max_bodies=max_bodies,
+                              path=p) for p in ("fused", "split")]
+    assert [l.step_path for l in lats] == ["fused", "split"]
+    for n in range(1, steps + 1):
+        for lat in lats:
+            if case.drift:
+                lat.set_bodies(*case.bodies_at(n))
+            lat.step(1)
+    return lats
+
+
+def _links_per_body(own, n_bodies):
+    """Cut links per body (spheres, then walls) of an owner map from
+    lbm_get_owner: fluid node x and direction c with x + c solid."""
+    import oracle
+    c, _, _ = oracle.tables()
+    n_walls = n_bodies[1]
+    cnt = np.zeros(int(own.max()) + 1 if own.max() >= 0 else 1, np.int64)
+    fluid = own < 0
+    for i in range(1, 19):
+        nb = np.roll(own, shift=(-int(c[i, 2]), -int(c[i, 1]), -int(c[i, 0])), axis=(0, 1, 2))
+        sel = fluid & (nb >= 0)
+        cnt += np.bincount(nb[sel], minlength=len(cnt))[:len(cnt)]
+    cnt = np.pad(cnt, (0, max(0, n_walls + n_bodies[0] - len(cnt))))
+    # library order: spheres (owner codes n_walls..), then walls (0..n_walls-1)
+    return np.concatenate([cnt[n_walls:n_walls + n_bodies[0]], cnt[:n_walls]])
+
+
+def _compare(lats):
+    fu, sp = lats
+    np.testing.assert_array_equal(fu.get_populations(), sp.get_populations())
+    own = fu.get_owner()
+    np.testing.assert_array_equal(own, sp.get_owner())
+    Ff, Tf = fu.get_forces()
+    Fs, Ts = sp.get_forces()
+    if len(Fs):
+        info = fu.info()
+        L = _links_per_body(own, (info["n_bodies"], info["n_walls"]))
+        # each term rounded to 2^-32 (error <= 2^-33), the split sums' FP64
+        # rounding bounded by L u times the largest partial sum
+        for A, B in ((Ff, Fs), (Tf, Ts)):
+            scale = np.max(np.abs(B), axis=1, keepdims=True) + 1.0
+            bar = L[:, None] * (2.0 ** -33 + 1e-15 * scale)
+            print(f"fused vs split: max |diff| {np.max(np.abs(A - B)):.2e}, "
+                  f"max |diff| / bar {np.max(np.abs(A - B) / np.maximum(bar, 1e-300)):.3f}")
+            assert np.all(np.abs(A - B) <= bar)
+    for lat in lats:
+        lat.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_paths_agree_on_a_drifting_duct(torch_stream, storage):
+    case = W.case_duct(nx=48, ny=40, nz=96, n_spheres=40, orifice_z=70, orifice_r_in=12, orifice_gap=4,
+                       pack_z=(6, 60), seed=31, drift=True)
+    _compare(_both(case, torch_stream, storage=storage, steps=10))
+
+
+@pytest.mark.parametrize("bb_mode", ["bouzidi", "halfway"])
+def test_paths_agree_on_random_walls_and_spheres(torch_stream, bb_mode):
+    from .test_gpu_edges import _random_case
+    for seed in (1, 2):
+        _compare(_both(_random_case(seed), torch_stream, bb_mode=bb_mode, steps=10))
+
+
+def test_paths_agree_with_many_tiny_spheres(torch_stream):
+    """Hundreds of tiny overlapping spheres per tile: the tile's force table
+    overflows into direct global sums."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    nx, ny, nz = 64, 16, 12
+    nb = 3000
+    case = W.Case(name="tiny", nx=nx, ny=ny, nz=nz, tau0=0.7, smag_c=0.1, X=rng.uniform(0, 1, (nb, 3)) * [nx, ny, nz],
+                  V=rng.normal(0.0, 0.02, (nb, 3)), Omega=rng.normal(0.0, 0.01, (nb, 3)), R=rng.uniform(0.4, 1.2, nb),
+                  u_init=rng.normal(0.0, 0.01, (3, nz, ny, nx)), drift=True)
+    _compare(_both(case, torch_stream, steps=4, max_bodies=nb))
+
+
+def test_paths_agree_with_the_inflow_plane(torch_stream):
+    """The inflow plane with spheres drifting across it."""
+    import dataclasses
+
+    from paper_1703_05158_amd import Lattice
+    from .test_gpu_zieb import _case
+    case, zp = _case()
+    X = np.array([[8.0, 7.0, 4.6], [16.0, 12.5, 5.2], [12.0, 9.0, 14.0]])
+    V = np.array([[0.02, 0.01, -0.03], [-0.01, 0.02, -0.035], [0.0, 0.0, 0.01]])
+    case = dataclasses.replace(case, X=X, V=V, R=np.array([3.0, 2.5, 3.5]), drift=True)
+    lats = []
+    for p in ("fused", "split"):
+        lat = Lattice.from_case(case, stream=torch_stream, init=False, path=p)
+        lat.set_zieb(*zp)
+        lat.init_fields(case.rho_init, case.u_init)
+        for n in range(1, 21):
+            lat.set_bodies(*case.bodies_at(n))
+            lat.step(1)
+        lats.append(lat)
+    assert lats[0].zieb_state() == lats[1].zieb_state()
+    _compare(lats)
+
+
+def test_split_path_meets_the_oracle(torch_stream):
+    """The split path stays a first-class path: the 32^3 case after 100 steps."""
+    case = W.case_box32()
+    o, lat = make_pair(case, stream=torch_stream)
+    lat.set_step_path("split")
+    advance(o, lat, case, 0, 100)
+    pe = pop_rel_err(o, lat)
+    fe, te = force_rel_err(o, lat)
+    print(f"split: pop {pe:.2e} F {fe:.2e} T {te:.2e}")
+    assert pe <= 1e-5 and fe <= 1e-4 and te <= 1e-4
+    lat.close()
+
+
+def test_profile_parts(torch_stream):
+    from paper_1703_05158_amd import Lattice
+    case = W.case_box(n=(48, 40, 36), n_spheres=6, radius=(2.5, 4.0), v_sigma=0.01, seed=3, drift=True)
+    for path in ("fused", "split"):
+        lat = Lattice.from_case(case, stream=torch_stream, path=path)
+        lat.profile(True)
+        for n in range(1, 6):
+            lat.set_bodies(*case.bodies_at(n))
+            lat.step(1)
+        parts, steps = lat.profile_read_parts()
+        ms, launches = lat.profile_read()
+        assert steps == 5 and launches == 5 and ms == parts["step"]
+        assert parts["geometry"] > 0 and parts["step"] > 0
+        if path == "fused":
+            assert parts["links"] == 0 and parts["forces"] > 0
+        else:
+            assert parts["links"] > 0 and parts["forces"] == 0
+        total = parts["geometry"] + parts["links"] + parts["step"] + parts["forces"]
+        assert parts["whole"] == pytest.approx(total, rel=1e-3, abs=1e-3)
+        lat.profile(False)
+        lat.close()
