@@ -280,6 +280,94 @@ def test_stream_brute_force_sphere(orc, seed):
     np.testing.assert_allclose(T[:nb], Tb[:nb], rtol=1e-12, atol=1e-15)
 
 
+def _link_q(xv, ck, Xb, R, box):
+    """Fraction of the link xv -> xv + ck inside the fluid, by bisection."""
+    d = xv - Xb
+    d -= box * np.round(d / box)
+    g = lambda s: ((d + s * ck) ** 2).sum() - R ** 2
+    lo, hi = 0.0, 1.0
+    assert g(lo) > 0 and g(hi) <= 0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if g(mid) > 0:
+            lo = mid
+        else:
+            hi = mid
+    return hi
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_bouzidi_reads_a_linear_field_at_the_characteristic_foot(orc, seed):
+    """Interpolated bounce-back (Sec. 2.3) follows the particle that reaches
+    the fluid node x along k' = opposite(k) after one step: it travels one
+    link length with a specular reflection at the wall, a fraction q of the
+    link x -> x + c_k away.  For q < 1/2 it left x - (1 - 2q) c_k moving
+    along k; the rule interpolates the k population linearly between x - c_k
+    and x, so when that population is a linear function G of the position on
+    the link's line, the value received is G at that foot point.  For
+    q >= 1/2 the particle reflected from x ends the step at x + (2q - 1) c_k
+    and the rule interpolates linearly, at x, between it and the k' particle
+    leaving x towards x - c_k; with the two values taken from one linear G
+    on the line (G at x + (2q - 1) c_k for the reflected one, G at x - c_k for
+    the other), the value received is G(x).  A swapped weight, a wrong
+    second population or a misplaced interpolation point in either branch
+    moves the point at which G is read.  Each link gets its own random G;
+    the sphere is at rest, so the moving-boundary term is zero; q by
+    bisection; links that would share a population are left out."""
+    import oracle
+    c, w, opp = oracle.tables()
+    rng = np.random.default_rng(40 + seed)
+    n = (18, 17, 19)
+    box = np.array(n, float)
+    X = np.array([[8.6 + 0.3 * seed, 8.2, 9.3 - 0.2 * seed]])
+    R = np.array([4.4 + 0.3 * seed])
+    o = _oracle(orc, n)
+    o.set_bodies(X, np.zeros((1, 3)), np.zeros((1, 3)), R)
+    o.init_fields()
+    own = o.own.reshape(n[2], n[1], n[0])
+    P = np.broadcast_to(w[:, None, None, None], (19, n[2], n[1], n[0])).copy()
+    set_by = {}
+    links = []
+    for z, y, x in zip(*np.nonzero(own < 0)):
+        xv = np.array([x, y, z])
+        for k in range(1, 19):
+            p = (xv + c[k]) % n
+            if own[p[2], p[1], p[0]] < 0:
+                continue
+            q = _link_q(xv.astype(float), c[k].astype(float), X[0], R[0], box)
+            back = (xv - c[k]) % n
+            behind = own[back[2], back[1], back[0]] < 0
+            a, b = w[k] * (1 + 0.1 * rng.standard_normal()), 0.05 * w[k] * rng.standard_normal()
+            if q < 0.5 and behind:
+                # G(s) = a + b s, s measured from x along c_k
+                entries = {(k, z, y, x): a, (k, back[2], back[1], back[0]): a - b}
+                expect = a - b * (1 - 2 * q)
+            elif q >= 0.5:
+                entries = {(k, z, y, x): a + b * (2 * q - 1), (opp[k], z, y, x): a - b}
+                expect = a
+            else:
+                continue
+            if any(e in set_by for e in entries):
+                continue
+            for e, v in entries.items():
+                set_by[e] = (z, y, x, k)
+                P[e] = v
+            links.append((opp[k], z, y, x, expect, q))
+    # every population a link reads must be one this test set for that link
+    for i, z, y, x, _, _ in links:
+        k = opp[i]
+        for e in ((k, z, y, x), (i, z, y, x)):
+            assert set_by.get(e, (z, y, x, k)) == (z, y, x, k)
+    o.P = np.ascontiguousarray(P.reshape(-1))
+    f, _, _ = o.stream()
+    f = f.reshape(19, n[2], n[1], n[0])
+    qs = np.array([l[5] for l in links])
+    assert (qs < 0.5).sum() > 100 and (qs >= 0.5).sum() > 100
+    got = np.array([f[i, z, y, x] for i, z, y, x, _, _ in links])
+    want = np.array([l[4] for l in links])
+    np.testing.assert_allclose(got, want, rtol=1e-14, atol=0)
+
+
 def test_bouzidi_continuous_at_half(orc):
     """Shifting a sphere so one link's q crosses 1/2 changes f only by O(shift)."""
     rng = np.random.default_rng(3)
