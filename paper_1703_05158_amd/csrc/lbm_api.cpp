@@ -39,6 +39,7 @@ struct lbm_ctx {
     int nb_state = 0, nb_next = 0;
     bool dirty = false;                // tab[1-ts] set since the last step / init
     double *walls = nullptr;
+    double *wrec = nullptr;            // max_walls * kBodyStride: the walls as link records {ref, U, 0, 0}
     int n_walls = 0;
     double *acc = nullptr;             // (max_bodies + max_walls) * 6: forces of the last step
     unsigned long long *fsum = nullptr; // fused step: fixed-point sums, (max_bodies + max_walls * kWallRep) * 6
@@ -211,6 +212,7 @@ LinkArgs link_args(const lbm_ctx *h)
     la.rho0 = (float)c.rho0;
     la.own = h->own;
     la.walls = h->walls;
+    la.wrec = h->wrec;
     la.wl_node = h->wl_node;
     la.wl_blk = h->wl_blk;
     la.wl_wblk = h->wl_wblk;
@@ -235,7 +237,7 @@ FusedArgs fused_args(const lbm_ctx *h)
     f.nb = h->nb_state;
     f.halfway = h->cfg.bb_mode == LBM_BB_HALFWAY;
     f.bodies = h->tab[h->ts];
-    f.walls = h->walls;
+    f.wrec = h->wrec;
     f.fsum = h->fsum;
     f.wall_base = h->cfg.max_bodies;
     return f;
@@ -275,6 +277,21 @@ hipError_t prof_mark(lbm_ctx *h, hipEvent_t *e)
 lbm_status clear_flag(lbm_ctx *h)
 {
     HIP_TRY(h, hipMemsetAsync(h->flag, 0, sizeof(int), h->stream));
+    return LBM_OK;
+}
+
+// The wall table (host, [n][kWallStride] = U, ref) as link records
+// {ref, U, Omega = 0, R = 0} on the device.
+lbm_status upload_wall_records(lbm_ctx *h, const double *wt, int n)
+{
+    std::vector<double> rec((size_t)kBodyStride * std::max(n, 1), 0.0);
+    for (int w = 0; w < n; ++w)
+        for (int a = 0; a < 3; ++a) {
+            rec[(size_t)w * kBodyStride + a] = wt[(size_t)w * kWallStride + 3 + a];
+            rec[(size_t)w * kBodyStride + 3 + a] = wt[(size_t)w * kWallStride + a];
+        }
+    HIP_TRY(h, hipMemcpyAsync(h->wrec, rec.data(), sizeof(double) * rec.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
 }
 
@@ -516,6 +533,7 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         dalloc(h, &h->tab[0], sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->tab[1], sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->walls, sizeof(double) * kWallStride * std::max(c.max_walls, 1)) != hipSuccess ||
+        dalloc(h, &h->wrec, sizeof(double) * kBodyStride * std::max(c.max_walls, 1)) != hipSuccess ||
         dalloc(h, &h->acc, sizeof(double) * 6 * std::max(nbt, 1)) != hipSuccess ||
         dalloc(h, &h->fsum, sizeof(unsigned long long) * std::max(fsum_entries(c), (size_t)1)) != hipSuccess ||
         dalloc(h, &h->order, sizeof(int) * std::max(c.max_bodies, 1)) != hipSuccess ||
@@ -550,7 +568,7 @@ void lbm_destroy(lbm_handle h)
     (void)hipStreamSynchronize(h->stream);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     free_wall_links(h);
-    void *dev[] = {h->pop[0], h->pop[1], h->own, h->wall_map, h->tab[0], h->tab[1], h->walls,
+    void *dev[] = {h->pop[0], h->pop[1], h->own, h->wall_map, h->tab[0], h->tab[1], h->walls, h->wrec,
                    h->acc, h->fsum, h->order, h->flag, h->scratch, h->zstate, h->zpart};
     for (void *p : dev)
         if (p) (void)hipFree(p);
@@ -593,6 +611,7 @@ lbm_status lbm_set_walls(lbm_handle h, const uint8_t *wall_id, int32_t n_walls, 
         }
     TRY(copy_sync(h, h->wall_map, wall_id, (size_t)h->N, hipMemcpyHostToDevice));
     TRY(copy_sync(h, h->walls, wt.data(), sizeof(double) * wt.size(), hipMemcpyHostToDevice));
+    TRY(upload_wall_records(h, wt.data(), n_walls));
     h->wall_host.assign(wall_id, wall_id + h->N);
     TRY(build_wall_links(h, wall_id, n_walls));
     h->n_walls = n_walls;
@@ -997,6 +1016,7 @@ lbm_status lbm_set_state(lbm_handle h, const void *buf, size_t bytes)
     TRY(copy_sync(h, h->tab[1 - h->ts], p, tabb, hipMemcpyHostToDevice));
     p += tabb;
     TRY(copy_sync(h, h->walls, p, wallb, hipMemcpyHostToDevice));
+    TRY(upload_wall_records(h, reinterpret_cast<const double *>(p), hd.n_walls));
     p += wallb;
     TRY(copy_sync(h, h->acc, p, accb, hipMemcpyHostToDevice));
     p += accb;

@@ -111,21 +111,30 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g
     const float uu = ux * ux + uy * uy + uz * uz;
     const float uF = ux * a.fx + uy * a.fy + uz * a.fz;
     if (a.flag && fluid && !(rho > 0.f && isfinite(uu))) atomicOr(a.flag, 1);
-    {   // rest population: equilibrium deviation w0 (rd - 1.5 rho uu), source -3 w0 cf uF
-        const float w = (float)wgt(0);
-        const float v = om1 * g[0] + om * w * (rd - 1.5f * rho * uu) - 3.0f * w * cf * uF;
-        St::stnt(at(dst, idx), fluid ? v : 0.0f);
-    }
+    // Post-collision deviation of direction i with weight w, for the pair
+    // (i, i+9), c = c_i:
+    //   equilibrium deviation  w (rd + rho (3 cu + 4.5 cu^2 - 1.5 uu)),
+    //   Guo source             w cf (3 (c.F - u.F) + 9 cu c.F),
+    // so om (feq - f) + source = w (A + cu (B cu + 9 cf cF)) +- w (3 om rho cu
+    // + 3 cf cF) with A = om (rd - 1.5 rho uu) - 3 cf uF, B = 4.5 om rho; the
+    // even part is shared by i and i+9, the odd part changes sign.  Factors
+    // are taken per weight class (1/18 for the axis pairs, 1/36 for the
+    // diagonal ones).
+    const float A = om * (rd - 1.5f * rho * uu) - 3.0f * cf * uF;
+    const float B = 4.5f * om * rho, D = 3.0f * om * rho;
+    const float w1 = (float)wgt(1), w2 = (float)wgt(4);
+    const float a1 = w1 * A, a2 = w2 * A, b1 = w1 * B, b2 = w2 * B, d1 = w1 * D, d2 = w2 * D;
+    const float e1 = 9.0f * w1 * cf, e2 = 9.0f * w2 * cf;   // times c.F: the source's cu term
+    const float o1 = 3.0f * w1 * cf, o2 = 3.0f * w2 * cf;   // times c.F: the source's odd term
+    St::stnt(at(dst, idx), fluid ? om1 * g[0] + (float)wgt(0) * A : 0.0f);
 #pragma unroll
     for (int i = 1; i <= 9; ++i) {
-        const float w = (float)wgt(i);
+        const bool axis = wgt(i) == wgt(1);
         const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
         const float cF = CX[i] * a.fx + CY[i] * a.fy + CZ[i] * a.fz;
-        // equilibrium deviation: even w (rd + rho (4.5 cu^2 - 1.5 uu)), odd 3 w rho cu
-        // Guo source: even w cf (9 cu cF - 3 uF), odd 3 w cf cF
-        const float ev = om * w * (rd + rho * (4.5f * cu * cu - 1.5f * uu)) + w * cf * (9.0f * cu * cF - 3.0f * uF);
-        const float od = 3.0f * w * (om * rho * cu + cf * cF);
-        const float vp = om1 * g[i] + ev + od, vm = om1 * g[i + 9] + ev - od;
+        const float ev = (axis ? a1 : a2) + cu * ((axis ? b1 : b2) * cu + (axis ? e1 : e2) * cF);
+        const float od = (axis ? d1 : d2) * cu + (axis ? o1 : o2) * cF;
+        const float vp = om1 * g[i] + (ev + od), vm = om1 * g[i + 9] + (ev - od);
         St::stnt(at(dst + (size_t)i * Ns, idx), fluid ? vp : 0.0f);
         St::stnt(at(dst + (size_t)(i + 9) * Ns, idx), fluid ? vm : 0.0f);
     }

@@ -38,30 +38,29 @@ namespace {
 
 using namespace dev;
 
-constexpr int kLinkCap = 1024;  // links of a tile held in LDS at once (rounds beyond)
-constexpr int kRec = 64;        // bodies of a tile with a slot in the LDS force table
+constexpr int kLinkCap = 1024;  // links of a tile listed at once (rounds beyond)
+constexpr int kRec = 16;        // bodies of a tile with a slot in the LDS force table
+constexpr int kCopies = 4;      // copies of the table's sums (by lane), so fewer lanes add to one address
 
-template <int TX, int TY, int TZ>
 struct FusedLds {
-    static constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, NH = HX * HY * HZ;
-    uint16_t own[NH + (NH & 1)];      // owner codes of the tile and its halo, x fastest
-    uint16_t item[kLinkCap];          // link: node of the tile << 5 | I
+    uint32_t item[kLinkCap];          // link: node << 24 | I << 19 | behind fluid << 18 | owner code of the solid
     float val[kQ - 1][kBlock];        // link value of population I at node n: val[I - 1][n]
     int key[kRec];                    // owner code of the body in a force slot, -1 free
-    unsigned long long sum[kRec][6];  // fixed-point F, T of that body
+    unsigned long long sum[kCopies][kRec][6];  // fixed-point F, T of that body
     int wtot[kBlock / 64];
 };
 
-// Coordinate v >= -1 taken into [0, n).
-__device__ __forceinline__ int wrap_mod(int v, int n)
-{
-    if (v < 0) return v + n;
-    if (v < n) return v;
-    return v - n < n ? v - n : v % n;
-}
-
+// v 2^32 rounded to the nearest integer, ties to even, as a two's-complement
+// 64-bit value.  While |v 2^32| < 2^51 one FP64 add of 1.5 2^52 leaves that
+// integer in the low mantissa bits; larger values take the library
+// conversion, which rounds the same way.
 __device__ __forceinline__ unsigned long long to_fix(double v)
 {
+    constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
+    if (__builtin_fabs(v) < 524288.0) {
+        const double t = __builtin_fma(v, kFixScale, kMagic);
+        return (unsigned long long)(__double_as_longlong(t) - __double_as_longlong(kMagic));
+    }
     return (unsigned long long)__double2ll_rn(v * kFixScale);
 }
 
@@ -73,77 +72,107 @@ __device__ __forceinline__ unsigned long long *fix_slot(const FusedArgs &f, int 
 }
 
 // Add one link's fixed-point force and torque to the tile's slot of body
-// `key`, or straight to the global sums when the table is full.
-template <class L>
-__device__ __forceinline__ void table_add(const FusedArgs &f, L &lds, int key, const unsigned long long (&v)[6],
+// `key` (the lane's copy of the sums), or straight to the global sums when
+// the table is full.  A slot is claimed once by compare-and-swap; later
+// lookups read it.
+__device__ __forceinline__ void table_add(const FusedArgs &f, FusedLds &lds, int key, const unsigned long long (&v)[6],
                                           int t)
 {
     int s = key & (kRec - 1);
 #pragma unroll 1
     for (int p = 0; p < kRec; ++p) {
-        const int cur = atomicCAS(&lds.key[s], -1, key);
+        int cur = __hip_atomic_load(&lds.key[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (cur == -1) cur = atomicCAS(&lds.key[s], -1, key);
         if (cur == -1 || cur == key) {
+            unsigned long long *d = lds.sum[threadIdx.x & (kCopies - 1)][s];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) atomicAdd(&lds.sum[s][c], v[c]);
+            for (int c = 0; c < 6; ++c)
+                if (v[c]) atomicAdd(d + c, v[c]);
             return;
         }
         s = (s + 1) & (kRec - 1);
     }
     unsigned long long *g = fix_slot(f, key, t);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) atomicAdd(g + c, v[c]);
+    for (int c = 0; c < 6; ++c)
+        if (v[c]) atomicAdd(g + c, v[c]);
 }
 
-// Link j of the tile's list: its value into lds.val[j], its momentum into
-// the force table.
+// Index offsets of a node's periodic neighbours along each axis: m = to the
+// node at coordinate - 1, p = to the node at + 1.
+struct NbOff {
+    int xm, xp, ym, yp, zm, zp;
+};
+
+__device__ __forceinline__ NbOff nb_off(int x, int y, int z, int nx, int ny, int nz)
+{
+    const int nxy = nx * ny;
+    NbOff o;
+    o.xm = x == 0 ? nx - 1 : -1;
+    o.xp = x + 1 >= nx ? 1 - nx : 1;
+    o.ym = y == 0 ? nxy - nx : -nx;
+    o.yp = y + 1 >= ny ? nx - nxy : nx;
+    o.zm = z == 0 ? nxy * (nz - 1) : -nxy;
+    o.zp = z + 1 >= nz ? nxy * (1 - nz) : nxy;
+    return o;
+}
+
+// Index of x - c_i, the source of the pull of population i (i compile-time).
+__device__ __forceinline__ uint32_t pull_src(uint32_t idx, const NbOff &o, int i)
+{
+    int d = 0;
+    if (CX[i] > 0) d += o.xm;
+    if (CX[i] < 0) d += o.xp;
+    if (CY[i] > 0) d += o.ym;
+    if (CY[i] < 0) d += o.yp;
+    if (CZ[i] > 0) d += o.zm;
+    if (CZ[i] < 0) d += o.zp;
+    return (uint32_t)((int)idx + d);
+}
+
+// The same for a direction known only at run time.
+__device__ __forceinline__ uint32_t pull_src_rt(uint32_t idx, const NbOff &o, int i)
+{
+    const int cx = dcx(i), cy = dcy(i), cz = dcz(i);
+    const int d = (cx > 0 ? o.xm : (cx < 0 ? o.xp : 0)) + (cy > 0 ? o.ym : (cy < 0 ? o.yp : 0)) +
+                  (cz > 0 ? o.zm : (cz < 0 ? o.zp : 0));
+    return (uint32_t)((int)idx + d);
+}
+
+// Link j of the tile's list: its value into LDS, its momentum into the force
+// table.  Walls are records like spheres: reference point, velocity, no
+// spin, q = 1/2 and no minimum image (their arm is about the reference
+// point).
 template <int S, int TX, int TY, int TZ>
-__device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds<TX, TY, TZ> &lds, int x0, int y0, int z0,
-                                           int j, int t)
+__device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds &lds, int x0, int y0, int z0, int j, int t)
 {
     using St = Store<S>;
     using T = typename St::T;
-    using Lds = FusedLds<TX, TY, TZ>;
-    constexpr int HX = Lds::HX, HY = Lds::HY;
     const StepArgs &a = f.s;
     const T *__restrict__ src = static_cast<const T *>(a.src);
     const size_t Ns = (size_t)a.Ns;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int it = lds.item[j];
-    const int nl = it >> 5, I = it & 31, K = opp(I);
-    const int lx = nl % TX, ly = (nl / TX) % TY, lz = nl / (TX * TY);
-    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-    const int cx = dcx(I), cy = dcy(I), cz = dcz(I);
-    const int hc = ((lz + 1) * HY + (ly + 1)) * HX + lx + 1;
-    const int off = cx + HX * (cy + HY * cz);
-    const int os = lds.own[hc - off];  // the solid node p = x - c_I
+    const uint32_t it = lds.item[j];
+    const int nl = (int)(it >> 24), I = (int)((it >> 19) & 31u), K = opp(I);
+    const bool behind = (it >> 18) & 1u;
+    const int os = (int)(it & 0x7FFFu);  // owner code of the solid node p = x - c_I
+    const int x = x0 + nl % TX, y = y0 + (nl / TX) % TY, z = z0 + nl / (TX * TY);
     const uint32_t xi = (uint32_t)(x + nx * (y + ny * z));
+    const bool sphere = os >= f.n_walls;
+    const bool exact_q = sphere && !f.halfway;
+    // the populations and the solid's record, in one round trip
     const float fk = St::ld(at(src + (size_t)K * Ns, xi));
-    float vr;
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (os < f.n_walls) {
-        const double *wl = f.walls + os * kWallStride;
-        vr = St::round(fk + wall_term(wl, I, a.rho0));
-        double a0, a1, a2;
-        wall_arm(wl, I, x, y, z, a0, a1, a2);
-        link_force(link_momentum(fk, vr, I, a.rho0), I, a0, a1, a2, acc);
-    } else {
-        // both second populations are loaded with the first, before q
-        // decides between them
-        const bool behind = lds.own[hc + off] >= kVacated;
-        const float fa = St::ld(at(src + (size_t)I * Ns, xi));
-        float fb = 0.0f;
-        if (behind) {
-            const uint32_t bi = (uint32_t)(wrap1(x + cx, nx) + nx * (wrap1(y + cy, ny) + ny * wrap1(z + cz, nz)));
-            fb = St::ld(at(src + (size_t)K * Ns, bi));
-        }
-        const SphereK k = sphere_k(f.bodies + (size_t)(os - f.n_walls) * kBodyStride);
-        const LinkGeo g = link_geo(k, f.halfway != 0, a.rho0, x, y, z, nx, ny, nz, I);
-        vr = St::round(link_value(g.q, fk, fa, fb, behind, g.mw));
-        double a0, a1, a2;
-        sphere_arm(g, I, a0, a1, a2);
-        link_force(link_momentum(fk, vr, I, a.rho0), I, a0, a1, a2, acc);
+    float fa = 0.0f, fb = 0.0f;
+    if (exact_q) {
+        fa = St::ld(at(src + (size_t)I * Ns, xi));
+        if (behind) fb = St::ld(at(src + (size_t)K * Ns, pull_src_rt(xi, nb_off(x, y, z, nx, ny, nz), K)));
     }
+    const double *B = sphere ? f.bodies + (size_t)(os - f.n_walls) * kBodyStride : f.wrec + (size_t)os * kBodyStride;
+    const LinkGeo g = link_geo(sphere_k(B), exact_q, sphere, a.rho0, x, y, z, nx, ny, nz, I);
+    const float vr = St::round(link_value(g.q, fk, fa, fb, behind, g.mw));
     lds.val[I - 1][nl] = vr;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    link_force(link_momentum(fk, vr, I, a.rho0), I, g, acc);
     unsigned long long v[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) v[c] = to_fix(acc[c]);
@@ -153,14 +182,11 @@ __device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds<TX, TY, 
 // Tile t of the lattice of f.  Every thread of the workgroup calls it (it
 // holds barriers); lds may be reused by the next call.
 template <int S, int TX, int TY, int TZ>
-__device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds<TX, TY, TZ> &lds)
+__device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &lds)
 {
     static_assert(TX * TY * TZ == kBlock, "tile must hold one workgroup");
     using St = Store<S>;
     using T = typename St::T;
-    using Lds = FusedLds<TX, TY, TZ>;
-    constexpr int HX = Lds::HX, HY = Lds::HY, NH = Lds::NH;
-    constexpr int HU = (NH + kBlock - 1) / kBlock;
     const StepArgs &a = f.s;
     const T *__restrict__ src = static_cast<const T *>(a.src);
     T *__restrict__ dst = static_cast<T *>(a.dst);
@@ -170,81 +196,88 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds<T
     const int tid = threadIdx.x;
     const int r = t / a.ntx;
     const int x0 = (t - r * a.ntx) * TX, y0 = (r % a.nty) * TY, z0 = (r / a.nty) * TZ;
-    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
-    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+    const int x = x0 + tid % TX, y = y0 + (tid / TX) % TY, z = z0 + tid / (TX * TY);
     const bool in = x < nx && y < ny && z < nz;
     const uint32_t idx = in ? (uint32_t)(x + nx * (y + ny * z)) : 0u;
+    const NbOff no = nb_off(x, y, z, nx, ny, nz);
+    auto src_idx = [&](int i) { return pull_src(idx, no, i); };
 
-    // 1. own code, halo codes, pulls
+    // 1. owner codes of the node and of its 18 pull sources
     const uint16_t o = in ? *at(a.own, idx) : uint16_t(0);
-    uint16_t hv[HU];
-#pragma unroll
-    for (int u = 0; u < HU; ++u) {
-        const int k = tid + u * kBlock;
-        hv[u] = 0;
-        if (k < NH) {
-            const int hx = k % HX, hr = k / HX;
-            const int gx = wrap_mod(x0 + hx - 1, nx), gy = wrap_mod(y0 + hr % HY - 1, ny);
-            const int gz = wrap_mod(z0 + hr / HY - 1, nz);
-            hv[u] = *at(a.own, (uint32_t)(gx + nx * (gy + ny * gz)));
-        }
-    }
     const bool fluid = in && o >= kVacated;
-    __syncthreads();  // the previous tile's readers of lds are done
-#pragma unroll
-    for (int u = 0; u < HU; ++u) {
-        const int k = tid + u * kBlock;
-        if (k < NH) lds.own[k] = hv[u];
-    }
-    for (int k = tid; k < kRec; k += kBlock) lds.key[k] = -1;
-    for (int k = tid; k < kRec * 6; k += kBlock) (&lds.sum[0][0])[k] = 0ull;
-    if (__syncthreads_or(fluid) == 0) return;
-
-    // 2. cut links: pull sources owned by a solid (not the inflow plane's
-    //    directions from the removed domain)
-    const int hc = ((lz + 1) * HY + (ly + 1)) * HX + lx + 1;
-    uint32_t m = 0;
+    uint16_t on[kQ];
+    uint32_t solid = 0;  // pull sources owned by a solid
     if (fluid) {
-        const bool plane = z == a.zieb_z;
 #pragma unroll
-        for (int i = 1; i < kQ; ++i) {
-            if (CZ[i] == 1 && plane) continue;
-            if (lds.own[hc - (CX[i] + HX * (CY[i] + HY * CZ[i]))] < kVacated) m |= 1u << i;
-        }
+        for (int i = 1; i < kQ; ++i) on[i] = *at(a.own, src_idx(i));
+#pragma unroll
+        for (int i = 1; i < kQ; ++i)
+            if (on[i] < kVacated) solid |= 1u << i;
     }
+    // cut links: not the inflow plane's directions from the removed domain
+    uint32_t m = solid;
+    if (z == a.zieb_z) {
+#pragma unroll
+        for (int i = 1; i < kQ; ++i)
+            if (CZ[i] == 1) m &= ~(1u << i);
+    }
+    __syncthreads();  // the previous tile's readers of lds are done
+    for (int k = tid; k < kRec; k += kBlock) lds.key[k] = -1;
+    for (int k = tid; k < kCopies * kRec * 6; k += kBlock) (&lds.sum[0][0][0])[k] = 0ull;
     int tot;
-    const int pos = block_scan(__popc(m), lds.wtot, tot);
-    // the link values go into LDS first; the pulls follow (the values pulled
-    // across cut links are then replaced)
-    for (int base = 0; base < tot; base += kLinkCap) {
-        if (base) __syncthreads();  // the previous round's list is processed
-        {
-            int k = pos;
-            uint32_t mm = m;
-            while (mm) {
-                const int i = __builtin_ctz(mm);
-                mm &= mm - 1;
-                if (k >= base && k < base + kLinkCap) lds.item[k - base] = (uint16_t)((tid << 5) | i);
+    const int pos = block_scan(__popc(m), lds.wtot, tot);  // its barrier also publishes the table's reset
+    if (tot == 0 && __syncthreads_or(fluid) == 0) return;
+
+    // 2. the tile's links, listed and spread over the workgroup, in rounds
+    //    of kLinkCap (the first from the codes in registers, later ones, rare,
+    //    load them again)
+    auto item = [&](int i, uint32_t code) {
+        const uint32_t behind = ((solid >> opp(i)) & 1u) ^ 1u;
+        return ((uint32_t)tid << 24) | ((uint32_t)i << 19) | (behind << 18) | code;
+    };
+    {
+        int k = pos;
+#pragma unroll
+        for (int i = 1; i < kQ; ++i)
+            if ((m >> i) & 1u) {
+                if (k < kLinkCap) lds.item[k] = item(i, on[i]);
                 ++k;
             }
+    }
+    for (int base = 0; base < tot; base += kLinkCap) {
+        if (base) {
+            __syncthreads();  // the previous round's list is processed
+            int k = pos;
+#pragma unroll 1
+            for (int i = 1; i < kQ; ++i)
+                if ((m >> i) & 1u) {
+                    if (k >= base && k < base + kLinkCap)
+                        lds.item[k - base] = item(i, *at(a.own, pull_src_rt(idx, no, i)));
+                    ++k;
+                }
         }
         __syncthreads();
         const int n = min(kLinkCap, tot - base);
         for (int j = tid; j < n; j += kBlock) fused_link<S, TX, TY, TZ>(f, lds, x0, y0, z0, j, t);
     }
-    __syncthreads();  // the link values and the tile's body sums are complete
-    // 4. the tile's body sums
-    if (tot > 0 && tid < kRec) {
-        const int key = lds.key[tid];
-        if (key >= 0) {
-            unsigned long long *gs = fix_slot(f, key, t);
+    if (tot > 0) {
+        __syncthreads();  // the link values and the tile's body sums are complete
+        // 4. the tile's body sums, the copies added up
+        if (tid < kRec) {
+            const int key = lds.key[tid];
+            if (key >= 0) {
+                unsigned long long *gs = fix_slot(f, key, t);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                const unsigned long long v = lds.sum[tid][c];
-                if (v) atomicAdd(gs + c, v);
+                for (int c = 0; c < 6; ++c) {
+                    unsigned long long v = 0ull;
+#pragma unroll
+                    for (int q = 0; q < kCopies; ++q) v += lds.sum[q][tid][c];
+                    if (v) atomicAdd(gs + c, v);
+                }
             }
         }
     }
+
     // 3. pull, collide and store (whole wavefronts; none with no fluid lane)
     if (!in || __ballot(fluid) == 0) return;
     float g[kQ];
@@ -252,16 +285,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds<T
 #pragma unroll
         for (int i = 0; i < kQ; ++i) g[i] = 0.0f;
     } else {
-        const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
-        const int yp = y + 1 == ny ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
-        const int zp = z + 1 == nz ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            const int sx = CX[i] > 0 ? xm : (CX[i] < 0 ? xp : x);
-            const int sy = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
-            const int sz = CZ[i] > 0 ? zm : (CZ[i] < 0 ? zp : z);
-            g[i] = St::ld(at(src + (size_t)i * Ns, (uint32_t)(sx + nx * (sy + ny * sz))));
-        }
+        for (int i = 0; i < kQ; ++i) g[i] = St::ld(at(src + (size_t)i * Ns, i ? src_idx(i) : idx));
 #pragma unroll
         for (int i = 1; i < kQ; ++i)
             if ((m >> i) & 1u) g[i] = lds.val[i - 1][tid];
@@ -270,10 +295,12 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds<T
     collide_store<S>(a, g, fluid, idx, dst);
 }
 
+// Six waves per SIMD: the LDS of a workgroup allows six per CU, and the
+// compiler then keeps the link phase within 80 VGPRs without spilling.
 template <int S, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_fused(FusedArgs f)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_fused(FusedArgs f)
 {
-    __shared__ FusedLds<TX, TY, TZ> lds;
+    __shared__ FusedLds lds;
     fused_tile<S, TX, TY, TZ>(f, xcd_remap(blockIdx.x, gridDim.x), lds);
 }
 
@@ -311,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_zero_fix(unsigned long long *p, int 
 template <int S, int TX, int TY, int TZ>
 __global__ __launch_bounds__(kBlock) void k_batch_fused(BatchStepArgs b)
 {
-    __shared__ FusedLds<TX, TY, TZ> lds;
+    __shared__ FusedLds lds;
     const int xcd = blockIdx.x & 7, stride = gridDim.x >> 3;
     const int lo = (int)((long long)b.total_tiles * xcd / 8), hi = (int)((long long)b.total_tiles * (xcd + 1) / 8);
     // the member of the previous tile is kept: a workgroup's next tile is

@@ -85,6 +85,7 @@ struct LinkArgs {
     void *pop;                    // current state: read at fluid nodes, written at solid nodes
     const double *bodies;         // [nb][kBodyStride]
     const double *walls;          // [n_walls][kWallStride]
+    const double *wrec;           // [n_walls][kBodyStride]: each wall as a record {ref, U, 0, 0} for the link arithmetic
     const uint32_t *wl_node;      // fluid nodes of the wall links, grouped by (wall, direction)
     const int *wl_blk;            // [n_wblk][3]: segment w * 18 + I - 1, begin, end
     int n_wblk;
@@ -110,7 +111,7 @@ struct FusedArgs {
     StepArgs s;                   // the step (its wall-total fields unused)
     int n_walls, nb, halfway;
     const double *bodies;         // [nb][kBodyStride], the current geometry
-    const double *walls;          // [n_walls][kWallStride]
+    const double *wrec;           // [n_walls][kBodyStride]: each wall as a record {ref, U, 0, 0}
     unsigned long long *fsum;     // fixed-point sums: [max_bodies][6], then [n_walls][kWallRep][6]
     int wall_base;                // max_bodies: first wall copy of fsum
 };

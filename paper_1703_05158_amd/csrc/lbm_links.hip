@@ -82,7 +82,7 @@ __device__ __forceinline__ LinkLoad link_load(const LinkArgs &a, const typename 
     const int x = wrap1(px + cx, nx), y = wrap1(py + cy, ny), z = wrap1(pz + cz, nz);
     l.pi = (uint32_t)(px + nx * (py + ny * pz));
     const uint32_t xi = (uint32_t)(x + nx * (y + ny * z));
-    l.g = link_geo(k, a.halfway != 0, a.rho0, x, y, z, nx, ny, nz, I);
+    l.g = link_geo(k, !a.halfway, true, a.rho0, x, y, z, nx, ny, nz, I);
     l.op = *at(a.own, l.pi);
     l.ox = *at(a.own, xi);
     l.fk = St::ld(at(pop + (size_t)K * Ns, xi));
@@ -110,9 +110,7 @@ __device__ __forceinline__ void link_finish(const LinkArgs &a, typename Store<S>
     const bool behind = l.ob >= kVacated;
     const float vr = St::round(link_value(l.g.q, l.fk, l.f2, l.f2, behind, l.g.mw));
     St::st(at(pop + (size_t)I * (size_t)a.Ns, l.pi), vr);
-    double a0, a1, a2;
-    sphere_arm(l.g, I, a0, a1, a2);
-    link_force(link_momentum(l.fk, vr, I, a.rho0), I, a0, a1, a2, acc);
+    link_force(link_momentum(l.fk, vr, I, a.rho0), I, l.g, acc);
 }
 
 constexpr int kItemCap = 4096;   // candidate links held at once
@@ -380,13 +378,11 @@ __device__ __forceinline__ void wall_block(const LinkArgs &a, int blk, double (*
     const int seg = a.wl_blk[3 * blk], beg = a.wl_blk[3 * blk + 1], end = a.wl_blk[3 * blk + 2];
     const int w = seg / (kQ - 1), I = seg - (kQ - 1) * w + 1, K = opp(I);
     const int cx = dcx(I), cy = dcy(I), cz = dcz(I);  // c_I = -c_K
-    const double *wl = a.walls + w * kWallStride;
-    const float add = wall_term(wl, I, a.rho0);
-    // momentum sum and its first moment about the reference point; the
-    // chunk's kWallChunk / kBlock links per thread have their loads in flight
-    // together
+    const SphereK wk = sphere_k(a.wrec + (size_t)w * kBodyStride);
+    // force and torque sums; the chunk's kWallChunk / kBlock links per
+    // thread have their loads in flight together
     constexpr int U = kWallChunk / kBlock;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     uint32_t xi[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -410,24 +406,16 @@ __device__ __forceinline__ void wall_block(const LinkArgs &a, int blk, double (*
         const uint32_t x = xi[u] % (uint32_t)nx, r = xi[u] / (uint32_t)nx;
         const uint32_t y = r % (uint32_t)ny, z = r / (uint32_t)ny;
         const int sx = wrap1((int)x - cx, nx), sy = wrap1((int)y - cy, ny), sz = wrap1((int)z - cz, a.nz);
-        const float vr = St::round(fk[u] + add);
+        const LinkGeo g = link_geo(wk, false, false, a.rho0, (int)x, (int)y, (int)z, nx, ny, a.nz, I);
+        const float vr = St::round(link_value(g.q, fk[u], fk[u], fk[u], false, g.mw));
         St::st(at(pop + (size_t)I * Ns, (uint32_t)(sx + nx * (sy + ny * sz))), vr);
-        const double mom = link_momentum(fk[u], vr, I, a.rho0);
-        v[0] += mom;
-        v[1] += mom * ((double)x - 0.5 * cx - wl[3]);
-        v[2] += mom * ((double)y - 0.5 * cy - wl[4]);
-        v[3] += mom * ((double)z - 0.5 * cz - wl[5]);
+        link_force(link_momentum(fk[u], vr, I, a.rho0), I, g, v);
     }
-    block_sum<4>(v, s_red);
+    block_sum<6>(v, s_red);
     if (threadIdx.x == 0) {
-        // F = S c_K, T = (sum mom arm) x c_K, c_K = -c_I
         double *o = a.wl_part + 6 * (size_t)blk;
-        o[0] = -v[0] * cx;
-        o[1] = -v[0] * cy;
-        o[2] = -v[0] * cz;
-        o[3] = -(v[2] * cz - v[3] * cy);
-        o[4] = -(v[3] * cx - v[1] * cz);
-        o[5] = -(v[1] * cy - v[2] * cx);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[c] = v[c];
     }
 }
 
@@ -503,7 +491,7 @@ __device__ __forceinline__ void adj_sphere_block(const AdjLinkArgs &g, int b, Sp
                 const uint32_t pi = (uint32_t)(px + nx * (py + ny * pz));
                 const uint32_t xi = (uint32_t)(x + nx * (y + ny * z));
                 if (*at(a.own, pi) != own_b || *at(a.own, xi) < kVacated) continue;
-                const float q = link_geo(k, a.halfway != 0, a.rho0, x, y, z, nx, ny, nz, I).q;
+                const float q = link_geo(k, !a.halfway, true, a.rho0, x, y, z, nx, ny, nz, I).q;
                 const float ckx = (float)(-cx);
                 const float m = g.mu ? *at(g.mu + (size_t)I * Ns, pi) : ckx;
                 float ak, ab = 0.f, ai = 0.f, aw;
