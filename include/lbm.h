@@ -166,7 +166,9 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *u);
  * BGK + Guo collision and the store (Sec. 2.2).  The force and torque sums
  * are kept as 64-bit fixed point with a resolution of 2^-32 per link
  * contribution (sums must stay below 2^31 in magnitude), so they are the same
- * bit for bit in any launch order, tile shape or batch.  On the split path
+ * bit for bit in any launch order, tile shape or batch.  The sums of a
+ * step are turned into FP64 forces by whichever comes first: the next fused
+ * step kernel, or lbm_get_forces / lbm_get_forces_device.  On the split path
  * (lbm_set_step_path) a link pass writes every link value into the solid
  * node's slot of the current state and reduces the forces per body in FP64,
  * then the pull-collide kernel pulls it; the populations are the same bit
@@ -239,9 +241,8 @@ enum {
     LBM_PROF_GEOMETRY = 0, /* inflow-plane update and re-rasterisation */
     LBM_PROF_LINKS = 1,    /* boundary-link pass (split path) */
     LBM_PROF_STEP = 2,     /* step kernel */
-    LBM_PROF_FORCES = 3,   /* force finish (fused path) */
-    LBM_PROF_WHOLE = 4,    /* the whole step, first event to last */
-    LBM_PROF_PARTS = 5
+    LBM_PROF_WHOLE = 3,    /* the whole step, first event to last */
+    LBM_PROF_PARTS = 4
 };
 lbm_status lbm_profile(lbm_handle h, int32_t enable);
 lbm_status lbm_profile_read(lbm_handle h, double *ms_total, int64_t *launches);

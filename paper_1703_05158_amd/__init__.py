@@ -35,7 +35,7 @@ STATUS = {0: "LBM_OK", 1: "LBM_ERR_ARG", 2: "LBM_ERR_OOM", 3: "LBM_ERR_HIP",
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 BB_MODE = {"bouzidi": 0, "halfway": 1}
 STEP_PATH = {"fused": 0, "split": 1}
-PROF_PARTS = ("geometry", "links", "step", "forces", "whole")
+PROF_PARTS = ("geometry", "links", "step", "whole")
 
 
 class LBMError(RuntimeError):

@@ -42,7 +42,14 @@ struct lbm_ctx {
     double *wrec = nullptr;            // max_walls * kBodyStride: the walls as link records {ref, U, 0, 0}
     int n_walls = 0;
     double *acc = nullptr;             // (max_bodies + max_walls) * 6: forces of the last step
-    unsigned long long *fsum = nullptr; // fused step: fixed-point sums, (max_bodies + max_walls * kWallRep) * 6
+    // fused step: fixed-point force sums, (max_bodies + max_walls * kWallRep) * 6
+    // each; the steps alternate between the two buffers.  The sums of the last
+    // step stay pending until lbm_get_forces[_device] or the next fused step
+    // turns them into acc.
+    unsigned long long *fsum[2] = {nullptr, nullptr};
+    int fcur = 0;                      // buffer of the next fused step
+    bool fpending = false;             // fsum[fcur ^ 1] holds the last step's sums, not yet in acc
+    int fpend_nb = 0, fpend_nw = 0;    // their body and wall counts
     int path = LBM_PATH_FUSED;         // lbm_step_path
     uint64_t geom_gen = 0;             // bumped whenever the geometry, the body force or the state is replaced
     int tile = kTile64x2x2;            // TileShape of the step kernel
@@ -77,7 +84,7 @@ struct lbm_ctx {
     // profiling: per step, events at the start, after the geometry update,
     // after the link pass (split path), after the step kernel and after the
     // force finish; events come from a pool that lives as long as the handle
-    std::vector<std::array<hipEvent_t, 5>> prof_ev;
+    std::vector<std::array<hipEvent_t, 4>> prof_ev;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::string err;
@@ -238,21 +245,43 @@ FusedArgs fused_args(const lbm_ctx *h)
     f.halfway = h->cfg.bb_mode == LBM_BB_HALFWAY;
     f.bodies = h->tab[h->ts];
     f.wrec = h->wrec;
-    f.fsum = h->fsum;
+    f.fsum = h->fsum[h->fcur];
     f.wall_base = h->cfg.max_bodies;
     return f;
 }
 
-FinishArgs finish_args(const lbm_ctx *h)
+// The pending sums of the last fused step, to be turned into acc.
+FinishArgs pending_finish(const lbm_ctx *h)
 {
     FinishArgs fa{};
-    fa.fsum = h->fsum;
+    fa.fsum = h->fsum[h->fcur ^ 1];
     fa.wall_base = h->cfg.max_bodies;
-    fa.nb = h->nb_state;
-    fa.n_walls = h->n_walls;
+    fa.nb = h->fpend_nb;
+    fa.n_walls = h->fpend_nw;
     fa.out = h->acc;
     return fa;
 }
+
+// Turn pending force sums into acc (and a copy in out2, if given).
+lbm_status finish_forces(lbm_ctx *h, double *out2)
+{
+    if (!h->fpending) return LBM_OK;
+    FinishArgs fa = pending_finish(h);
+    fa.out2 = out2;
+    HIP_TRY(h, launch_finish(fa, h->stream));
+    h->fpending = false;
+    return LBM_OK;
+}
+
+// Clear both force-sum buffers and any pending step.
+lbm_status reset_sums(lbm_ctx *h)
+{
+    for (int k = 0; k < 2; ++k) HIP_TRY(h, launch_zero_fix(h->fsum[k], (int)fsum_entries(h->cfg), h->stream));
+    h->fpending = false;
+    h->fcur = 0;
+    return LBM_OK;
+}
+
 
 // An event of the handle's pool for the profile of one step.
 hipError_t prof_event(lbm_ctx *h, hipEvent_t *e)
@@ -299,8 +328,11 @@ lbm_status upload_wall_records(lbm_ctx *h, const double *wt, int n)
 lbm_status rasterize_full(lbm_ctx *h)
 {
     GeomArgs g = geom(h);
+    g.bodies2 = g.bodies;  // stamp only
+    g.nb2 = g.nb;
+    g.nb = 0;
     HIP_TRY(h, launch_walls_init(h->wall_map, h->own, h->N, h->stream));
-    HIP_TRY(h, launch_stamp(g, h->stream));
+    HIP_TRY(h, launch_geometry(h->cfg.storage, g, h->stream));
     return LBM_OK;
 }
 
@@ -308,15 +340,10 @@ lbm_status rasterize_full(lbm_ctx *h)
 // the last step), refilling uncovered nodes in the current population buffer.
 lbm_status rasterize_update(lbm_ctx *h)
 {
-    GeomArgs old_g = geom(h);
-    GeomArgs new_g = old_g;
-    new_g.bodies = h->tab[1 - h->ts];
-    new_g.nb = h->nb_next;
-    GeomArgs vac = old_g;
-    vac.bodies2 = new_g.bodies;
-    vac.nb2 = new_g.nb;
-    HIP_TRY(h, launch_vacate(h->cfg.storage, vac, h->stream));
-    HIP_TRY(h, launch_stamp(new_g, h->stream));
+    GeomArgs g = geom(h);
+    g.bodies2 = h->tab[1 - h->ts];
+    g.nb2 = h->nb_next;
+    HIP_TRY(h, launch_geometry(h->cfg.storage, g, h->stream));
     h->ts = 1 - h->ts;
     h->nb_state = h->nb_next;
     h->dirty = false;
@@ -491,7 +518,7 @@ lbm_status build_wall_links(lbm_ctx *h, const uint8_t *wall, int n_walls)
 
 extern "C" {
 
-int32_t lbm_version(void) { return 10100; }
+int32_t lbm_version(void) { return 10200; }
 
 const char *lbm_last_error(lbm_handle h) { return h ? h->err.c_str() : kNullHandle; }
 
@@ -535,7 +562,8 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         dalloc(h, &h->walls, sizeof(double) * kWallStride * std::max(c.max_walls, 1)) != hipSuccess ||
         dalloc(h, &h->wrec, sizeof(double) * kBodyStride * std::max(c.max_walls, 1)) != hipSuccess ||
         dalloc(h, &h->acc, sizeof(double) * 6 * std::max(nbt, 1)) != hipSuccess ||
-        dalloc(h, &h->fsum, sizeof(unsigned long long) * std::max(fsum_entries(c), (size_t)1)) != hipSuccess ||
+        dalloc(h, &h->fsum[0], sizeof(unsigned long long) * std::max(fsum_entries(c), (size_t)1)) != hipSuccess ||
+        dalloc(h, &h->fsum[1], sizeof(unsigned long long) * std::max(fsum_entries(c), (size_t)1)) != hipSuccess ||
         dalloc(h, &h->order, sizeof(int) * std::max(c.max_bodies, 1)) != hipSuccess ||
         dalloc(h, &h->zstate, sizeof(ZiebState)) != hipSuccess ||
         dalloc(h, &h->zpart, sizeof(double) * (3 * kZiebMaxBlocks + 1)) != hipSuccess ||
@@ -551,7 +579,9 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         hipMemsetAsync(h->pop[0], 0, popb, h->stream) != hipSuccess ||
         hipMemsetAsync(h->pop[1], 0, popb, h->stream) != hipSuccess ||
         hipMemsetAsync(h->acc, 0, sizeof(double) * 6 * std::max(nbt, 1), h->stream) != hipSuccess ||
-        hipMemsetAsync(h->fsum, 0, sizeof(unsigned long long) * std::max(fsum_entries(c), (size_t)1), h->stream) !=
+        hipMemsetAsync(h->fsum[0], 0, sizeof(unsigned long long) * std::max(fsum_entries(c), (size_t)1), h->stream) !=
+            hipSuccess ||
+        hipMemsetAsync(h->fsum[1], 0, sizeof(unsigned long long) * std::max(fsum_entries(c), (size_t)1), h->stream) !=
             hipSuccess ||
         hipMemsetAsync(h->flag, 0, sizeof(int), h->stream) != hipSuccess ||
         hipMemsetAsync(h->zpart + 3 * kZiebMaxBlocks, 0, sizeof(double), h->stream) != hipSuccess)
@@ -569,7 +599,7 @@ void lbm_destroy(lbm_handle h)
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     free_wall_links(h);
     void *dev[] = {h->pop[0], h->pop[1], h->own, h->wall_map, h->tab[0], h->tab[1], h->walls, h->wrec,
-                   h->acc, h->fsum, h->order, h->flag, h->scratch, h->zstate, h->zpart};
+                   h->acc, h->fsum[0], h->fsum[1], h->order, h->flag, h->scratch, h->zstate, h->zpart};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (h->pinned) (void)hipHostFree(h->pinned);
@@ -736,7 +766,7 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *u)
     GeomArgs g = geom(h);
     HIP_TRY(h, launch_init_pop(h->cfg.storage, g, rho_dev, u_dev, h->stream));
     HIP_TRY(h, launch_zero(h->acc, 6 * (h->cfg.max_bodies + h->cfg.max_walls), h->stream));
-    HIP_TRY(h, launch_zero_fix(h->fsum, (int)fsum_entries(h->cfg), h->stream));
+    TRY(reset_sums(h));
     TRY(clear_flag(h));
     const ZiebState z0{-1.0, 0.0, 0.0, 0.0};
     HIP_TRY(h, hipMemcpyAsync(h->zstate, &z0, sizeof z0, hipMemcpyHostToDevice, h->stream));
@@ -752,12 +782,13 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *u)
 namespace {
 
 // One step of the handle: inflow-plane update, re-rasterisation when the
-// bodies changed, then the fused step kernel and the force finish, or (the
-// split path) the boundary-link pass and the pull-collide kernel.
+// bodies changed, then the fused step kernel (which also finishes the force
+// sums of the step before, if nothing read them), or (the split path) the
+// boundary-link pass and the pull-collide kernel.
 lbm_status step_once(lbm_ctx *h)
 {
     const lbm_config &c = h->cfg;
-    std::array<hipEvent_t, 5> ev{};
+    std::array<hipEvent_t, 4> ev{};
     if (h->prof) HIP_TRY(h, prof_mark(h, &ev[0]));
     // the inflow plane's mean velocity is that of the current state, on its
     // own geometry: taken before the spheres of this step are drawn
@@ -766,11 +797,19 @@ lbm_status step_once(lbm_ctx *h)
     if (h->prof) HIP_TRY(h, prof_mark(h, &ev[1]));
     if (h->path == LBM_PATH_FUSED) {
         ev[2] = ev[1];
-        HIP_TRY(h, launch_fused(c.storage, fused_args(h), h->stream));
+        FusedArgs f = fused_args(h);
+        if (h->fpending) {  // the last step's forces, unread: into acc by this launch
+            f.fin = pending_finish(h);
+            h->fpending = false;
+        }
+        HIP_TRY(h, launch_fused(c.storage, f, h->stream));
         if (h->prof) HIP_TRY(h, prof_mark(h, &ev[3]));
-        HIP_TRY(h, launch_finish(finish_args(h), h->stream));
-        if (h->prof) HIP_TRY(h, prof_mark(h, &ev[4]));
+        h->fpend_nb = h->nb_state;
+        h->fpend_nw = h->n_walls;
+        h->fpending = true;
+        h->fcur ^= 1;
     } else {
+        TRY(finish_forces(h, nullptr));
         LinkArgs la = link_args(h);
         HIP_TRY(h, launch_links(c.storage, la, h->stream));
         if (h->prof) HIP_TRY(h, prof_mark(h, &ev[2]));
@@ -783,7 +822,6 @@ lbm_status step_once(lbm_ctx *h)
         a.wsum_out = h->acc;
         HIP_TRY(h, launch_step(c.storage, a, h->stream));
         if (h->prof) HIP_TRY(h, prof_mark(h, &ev[3]));
-        ev[4] = ev[3];
     }
     if (h->prof) h->prof_ev.push_back(ev);
     h->cur = 1 - h->cur;
@@ -822,6 +860,7 @@ lbm_status lbm_get_forces(lbm_handle h, double *F, double *T)
     if (st != LBM_OK) return st;
     const int nbt = h->nb_state + h->n_walls;
     if (nbt > 0 && (!F || !T)) return fail(h, LBM_ERR_ARG, "NULL output");
+    TRY(finish_forces(h, nullptr));
     // through the pinned staging buffer: one DMA, no per-call allocation
     const double *buf = h->forces_pin;
     HIP_TRY(h, hipMemcpyAsync(h->forces_pin, h->acc, sizeof(double) * 6 * nbt, hipMemcpyDeviceToHost, h->stream));
@@ -841,6 +880,7 @@ lbm_status lbm_get_forces_device(lbm_handle h, double *d_out)
     if (st != LBM_OK) return st;
     const int nbt = h->nb_state + h->n_walls;
     if (nbt > 0 && !d_out) return fail(h, LBM_ERR_ARG, "NULL output");
+    if (h->fpending) return finish_forces(h, d_out);  // one launch: acc and the caller's copy
     if (nbt > 0)
         HIP_TRY(h, hipMemcpyAsync(d_out, h->acc, sizeof(double) * 6 * nbt, hipMemcpyDeviceToDevice, h->stream));
     return LBM_OK;
@@ -928,6 +968,7 @@ lbm_status lbm_get_state(lbm_handle h, void *buf, size_t *bytes)
         return LBM_OK;
     }
     if (*bytes < need) return fail(h, LBM_ERR_ARG, "buffer of %zu bytes < %zu needed", *bytes, need);
+    TRY(finish_forces(h, nullptr));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     StateHeader hd{};
     memcpy(hd.magic, "LBMSTAT1", 8);
@@ -1028,7 +1069,7 @@ lbm_status lbm_set_state(lbm_handle h, const void *buf, size_t bytes)
     h->steps_done = hd.steps_done;
     h->initialized = true;
     h->geom_gen++;
-    HIP_TRY(h, launch_zero_fix(h->fsum, (int)fsum_entries(h->cfg), h->stream));
+    TRY(reset_sums(h));
     TRY(clear_flag(h));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
@@ -1086,8 +1127,8 @@ lbm_status lbm_profile_read_parts(lbm_handle h, double *ms, int64_t *steps)
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     double tot[LBM_PROF_PARTS] = {0.0};
     for (const auto &e : h->prof_ev) {
-        // parts: geometry, link pass, step kernel, forces, then the whole step
-        const int from[LBM_PROF_PARTS] = {0, 1, 2, 3, 0}, to[LBM_PROF_PARTS] = {1, 2, 3, 4, 4};
+        // parts: geometry, link pass, step kernel, then the whole step
+        const int from[LBM_PROF_PARTS] = {0, 1, 2, 0}, to[LBM_PROF_PARTS] = {1, 2, 3, 3};
         for (int p = 0; p < LBM_PROF_PARTS; ++p) {
             if (e[from[p]] == e[to[p]]) continue;
             float v = 0.f;
@@ -1219,6 +1260,7 @@ lbm_status lbm_drag_gradient(lbm_handle h, int32_t nsteps, int32_t ckpt, double 
         }
     }
     h->prof = prof;
+    TRY(finish_forces(h, nullptr));
     std::vector<double> acc_h((size_t)6 * nbt);
     TRY(copy_sync(h, acc_h.data(), h->acc, sizeof(double) * 6 * nbt, hipMemcpyDeviceToHost));
     double Jv = 0.0;
@@ -1347,7 +1389,7 @@ lbm_status lbm_autotune_tile(lbm_handle h, int32_t trial_steps, const char *cach
         }
     }
     set_tile_shape(h, best);
-    HIP_TRY(h, launch_zero_fix(h->fsum, (int)fsum_entries(h->cfg), h->stream));
+    HIP_TRY(h, launch_zero_fix(h->fsum[h->fcur], (int)fsum_entries(h->cfg), h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     if (shape_out) *shape_out = best;
     if (cache_path) {
@@ -1459,6 +1501,7 @@ lbm_status batch_build(lbm_batch_ctx *b)
         lbm_ctx *h = b->m[(size_t)i];
         BatchMember &bm = hm[(size_t)i];
         bm.f = fused_args(h);
+        bm.f.fin = FinishArgs{};
         StepArgs &st = bm.f.s;
         st.flag = nullptr;
         st.tile = b->shape;
@@ -1466,7 +1509,7 @@ lbm_status batch_build(lbm_batch_ctx *b)
         st.nty = (h->cfg.ny + TY - 1) / TY;
         st.ntz = (h->cfg.nz + TZ - 1) / TZ;
         st.n_tiles = st.ntx * st.nty * st.ntz;
-        bm.fin = finish_args(h);
+        bm.fin = FinishArgs{h->fsum[h->fcur], h->cfg.max_bodies, h->nb_state, h->n_walls, h->acc, nullptr};
         bm.pop[0] = h->pop[0];
         bm.pop[1] = h->pop[1];
         bm.tile_begin = tiles;
@@ -1572,6 +1615,7 @@ lbm_status batch_sync_members(lbm_batch_ctx *b)
         if (h->dirty) return bfail(b, LBM_ERR_STATE, "member %d: bodies set since the batch was built", i);
         if (h->geom_gen != b->gen[(size_t)i])
             return bfail(b, LBM_ERR_STATE, "member %d: geometry or state replaced since the batch was built", i);
+        if (finish_forces(h, nullptr) != LBM_OK) return bfail(b, LBM_ERR_HIP, "member %d: %s", i, h->err.c_str());
         BHIP_TRY(b, hipStreamSynchronize(h->stream));
         b->h_cur[i] = h->cur;
     }
@@ -1582,7 +1626,7 @@ lbm_status batch_sync_members(lbm_batch_ctx *b)
 // Clear the members' force sums (after launches that only time the kernel).
 lbm_status batch_zero_sums(lbm_batch_ctx *b)
 {
-    for (lbm_ctx *h : b->m) BHIP_TRY(b, launch_zero_fix(h->fsum, (int)fsum_entries(h->cfg), b->stream));
+    for (lbm_ctx *h : b->m) BHIP_TRY(b, launch_zero_fix(h->fsum[h->fcur], (int)fsum_entries(h->cfg), b->stream));
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     return LBM_OK;
 }

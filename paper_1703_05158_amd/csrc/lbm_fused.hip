@@ -295,33 +295,47 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
     collide_store<S>(a, g, fluid, idx, dst);
 }
 
+// Force entry i of a step (spheres, then walls) from its fixed-point sums,
+// which are cleared.
+__device__ __forceinline__ void finish_value(const FinishArgs &fa, int i)
+{
+    const int ns = 6 * fa.nb;
+    unsigned long long sum;
+    if (i < ns) {
+        sum = fa.fsum[i];
+        fa.fsum[i] = 0ull;
+    } else {
+        const int w = (i - ns) / 6, c = (i - ns) % 6;
+        unsigned long long *p = fa.fsum + 6 * ((size_t)fa.wall_base + (size_t)w * kWallRep) + c;
+        sum = 0ull;
+        for (int r = 0; r < kWallRep; ++r) {
+            sum += p[6 * r];
+            p[6 * r] = 0ull;
+        }
+    }
+    const double v = (double)(long long)sum * (1.0 / kFixScale);
+    fa.out[i] = v;
+    if (fa.out2) fa.out2[i] = v;
+}
+
 // Six waves per SIMD: the LDS of a workgroup allows six per CU, and the
 // compiler then keeps the link phase within 80 VGPRs without spilling.
 template <int S, int TX, int TY, int TZ>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_fused(FusedArgs f)
 {
     __shared__ FusedLds lds;
+    // the previous step's forces, if nobody has read them yet (their sums
+    // are in the other buffer)
+    if (f.fin.fsum)
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < 6 * (f.fin.nb + f.fin.n_walls); i += gridDim.x * kBlock)
+            finish_value(f.fin, i);
     fused_tile<S, TX, TY, TZ>(f, xcd_remap(blockIdx.x, gridDim.x), lds);
 }
 
 __global__ __launch_bounds__(kBlock) void k_finish(FinishArgs fa)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    const int ns = 6 * fa.nb;
-    if (i < ns) {
-        const unsigned long long v = fa.fsum[i];
-        fa.fsum[i] = 0ull;
-        fa.out[i] = (double)(long long)v * (1.0 / kFixScale);
-    } else if (i < ns + 6 * fa.n_walls) {
-        const int w = (i - ns) / 6, c = (i - ns) % 6;
-        unsigned long long *p = fa.fsum + 6 * ((size_t)fa.wall_base + (size_t)w * kWallRep) + c;
-        unsigned long long s = 0ull;
-        for (int r = 0; r < kWallRep; ++r) {
-            s += p[6 * r];
-            p[6 * r] = 0ull;
-        }
-        fa.out[i] = (double)(long long)s * (1.0 / kFixScale);
-    }
+    if (i < 6 * (fa.nb + fa.n_walls)) finish_value(fa, i);
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero_fix(unsigned long long *p, int n)
@@ -377,23 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_finish(BatchStepArgs b)
         if (b.members[mid].force_begin <= g) m = mid;
         else top = mid;
     }
-    const FinishArgs &fa = b.members[m].fin;
-    const int i = g - b.members[m].force_begin;
-    const int ns = 6 * fa.nb;
-    if (i < ns) {
-        const unsigned long long v = fa.fsum[i];
-        fa.fsum[i] = 0ull;
-        fa.out[i] = (double)(long long)v * (1.0 / kFixScale);
-    } else {
-        const int w = (i - ns) / 6, c = (i - ns) % 6;
-        unsigned long long *p = fa.fsum + 6 * ((size_t)fa.wall_base + (size_t)w * kWallRep) + c;
-        unsigned long long s = 0ull;
-        for (int r = 0; r < kWallRep; ++r) {
-            s += p[6 * r];
-            p[6 * r] = 0ull;
-        }
-        fa.out[i] = (double)(long long)s * (1.0 / kFixScale);
-    }
+    finish_value(b.members[m].fin, g - b.members[m].force_begin);
 }
 
 __global__ __launch_bounds__(kBlock) void k_batch_flip(int *cur, int n)

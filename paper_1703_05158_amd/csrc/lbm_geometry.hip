@@ -1,15 +1,19 @@
 // Owner-map maintenance and state import/export kernels (gfx950).
 //
-// The owner map is kept incrementally when spheres move.  Vacate: every node
-// a sphere owned in the previous geometry and no longer covers is refilled
-// with the equilibrium at rho0 and the velocity it had as a solid (the
-// solid-side Maxwell equilibrium of Sec. 2.3) and marked fluid.  Stamp: the
-// new spheres take their nodes with an atomic minimum (walls and lower
-// sphere indices win; nodes a sphere keeps need no atomic).  A node vacated
-// by one sphere and stamped by another is refilled for nothing: a solid
-// node's populations are never read.  One workgroup per sphere walks the
-// sphere's bounding box: vacate with an 8x8x4 thread block, stamp in chunks
-// whose owner codes each thread loads together.
+// The owner map is kept incrementally when spheres move, in one launch with
+// one workgroup per new sphere and one per old sphere, in any order:
+//  - stamp: sphere c takes every node of its new ball unless a wall or a
+//    lower-index sphere whose new ball also covers it owns the node; it takes
+//    the node by compare-and-swap from any other owner (a higher index, the
+//    fluid, or a lower index that is leaving the node);
+//  - vacate: a node the previous geometry's sphere a owned and its new ball
+//    does not cover turns fluid by compare-and-swap from a, if no sphere has
+//    taken it, and is refilled with the equilibrium at rho0 and the velocity
+//    it had as a solid (the solid-side Maxwell equilibrium of Sec. 2.3).
+// Every node ends with the owner of the new geometry whatever the order of
+// the workgroups: the lowest-index sphere whose new ball covers it (walls
+// first), else fluid.  A node refilled and then taken by another sphere was
+// refilled for nothing: a solid node's populations are never read.
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -35,7 +39,7 @@ __device__ __forceinline__ float foff(int v, double c, int n) { return (float)mi
 // tests are left to f, which sees every node either test could accept).
 template <typename F>
 __device__ __forceinline__ void walk_leaving(const double *B, const double *Bn, bool keeps, int nx, int ny, int nz,
-                                             F &&f)
+                                             int tx, int ty, int tz, F &&f)
 {
     const Box bx = body_box(B, 0);
     const float R2 = (float)(B[9] * B[9]);
@@ -43,14 +47,14 @@ __device__ __forceinline__ void walk_leaving(const double *B, const double *Bn, 
     const float Rn2 = keeps ? (float)(Bn[9] * Bn[9]) : 0.0f;
     const float in2 = keeps ? Rn2 - (0.01f + 1e-5f * Rn2) : -1.0f;
     const double cx = keeps ? Bn[0] : 0.0, cy = keeps ? Bn[1] : 0.0, cz = keeps ? Bn[2] : 0.0;
-    for (int kz = threadIdx.z; kz < bx.ez; kz += 4) {
+    for (int kz = tz; kz < bx.ez; kz += 4) {
         const int vz = bx.z0 + kz, pz = wrap1(vz, nz);
         const float dz = foff(vz, B[2], nz), ez = foff(vz, cz, nz);
-        for (int ky = threadIdx.y; ky < bx.ey; ky += 8) {
+        for (int ky = ty; ky < bx.ey; ky += 8) {
             const int vy = bx.y0 + ky, py = wrap1(vy, ny);
             const float dy = foff(vy, B[1], ny), ey = foff(vy, cy, ny);
             const float dyz = dy * dy + dz * dz, eyz = ey * ey + ez * ez;
-            for (int kx = threadIdx.x; kx < bx.ex; kx += 8) {
+            for (int kx = tx; kx < bx.ex; kx += 8) {
                 const int vx = bx.x0 + kx;
                 const float dx = foff(vx, B[0], nx);
                 if (dx * dx + dyz > out2) continue;
@@ -69,6 +73,7 @@ constexpr int kBoxU = 8;  // box nodes per thread whose owner loads are in fligh
 
 // Node k (x fastest) of a body's box: its coordinates and index.
 struct BoxNode {
+    int vx, vy, vz;   // unwrapped
     int px, py, pz;
     uint32_t n;
 };
@@ -77,54 +82,83 @@ __device__ __forceinline__ BoxNode box_node(const Box &bx, int k, int nx, int ny
 {
     const int kx = k % bx.ex, r = k / bx.ex;
     BoxNode v;
-    v.px = wrap1(bx.x0 + kx, nx);
-    v.py = wrap1(bx.y0 + r % bx.ey, ny);
-    v.pz = wrap1(bx.z0 + r / bx.ey, nz);
+    v.vx = bx.x0 + kx;
+    v.vy = bx.y0 + r % bx.ey;
+    v.vz = bx.z0 + r / bx.ey;
+    v.px = wrap1(v.vx, nx);
+    v.py = wrap1(v.vy, ny);
+    v.pz = wrap1(v.vz, nz);
     v.n = (uint32_t)(v.px + nx * (v.py + ny * v.pz));
     return v;
 }
 
 // The nodes of a body's box in chunks of kBoxU per thread (a 1-D
 // workgroup): the owner codes of a chunk are loaded together (keep(node)
-// selects the nodes to load), then act(node, owner) runs on each loaded node.
-template <typename Keep, typename Act>
+// selects the nodes to load), then act(node, owner) runs on each loaded node
+// whose owner passes want(owner).  Only the box index k and the node index
+// are held across the loads; the coordinates are made again for act.
+template <typename Keep, typename Want, typename Act>
 __device__ __forceinline__ void box_chunks(const Box &bx, int nx, int ny, int nz, const uint16_t *own, Keep &&keep,
-                                           Act &&act)
+                                           Want &&want, Act &&act)
 {
     const int total = bx.ex * bx.ey * bx.ez;
     for (int base = 0; base < total; base += kBoxU * kBlock) {
-        BoxNode v[kBoxU];
+        uint32_t n[kBoxU];
         uint16_t o[kBoxU];
-        bool ld[kBoxU];
+        unsigned ld = 0;
 #pragma unroll
         for (int u = 0; u < kBoxU; ++u) {
             const int k = base + u * kBlock + (int)threadIdx.x;
-            ld[u] = false;
             o[u] = 0;
+            n[u] = 0;
             if (k < total) {
-                v[u] = box_node(bx, k, nx, ny, nz);
-                ld[u] = keep(v[u]);
-                if (ld[u]) o[u] = own[v[u].n];
+                const BoxNode v = box_node(bx, k, nx, ny, nz);
+                if (keep(v)) {
+                    ld |= 1u << u;
+                    n[u] = v.n;
+                    o[u] = own[v.n];
+                }
             }
         }
 #pragma unroll
         for (int u = 0; u < kBoxU; ++u)
-            if (ld[u]) act(v[u], o[u]);
+            if (((ld >> u) & 1u) && want(o[u])) act(box_node(bx, base + u * kBlock + (int)threadIdx.x, nx, ny, nz), o[u]);
     }
 }
 
-__device__ __forceinline__ void atomic_min_u16(uint16_t *addr, uint16_t val)
+// Compare-and-swap of a 16-bit owner code (through its 32-bit word): the
+// code found (expect on success).
+__device__ __forceinline__ uint16_t cas_u16(uint16_t *addr, uint16_t expect, uint16_t val)
 {
     unsigned int *w = (unsigned int *)((uintptr_t)addr & ~(uintptr_t)3);
     const unsigned int sh = ((uintptr_t)addr & 2) ? 16u : 0u;
     unsigned int old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     while (true) {
-        const unsigned int cur = (old >> sh) & 0xffffu;
-        if (cur <= val) return;
+        const uint16_t cur = (uint16_t)((old >> sh) & 0xffffu);
+        if (cur != expect) return cur;
         const unsigned int nw = (old & ~(0xffffu << sh)) | ((unsigned int)val << sh);
         const unsigned int prev = atomicCAS(w, old, nw);
-        if (prev == old) return;
-        old = prev;
+        if (prev == old) return expect;
+        old = prev;  // this code or the other half of the word changed
+    }
+}
+
+// Sphere `id` (new geometry) takes node v, found with owner o.
+__device__ __forceinline__ void stamp_node(const GeomArgs &g, uint16_t *own, const BoxNode &v, uint16_t o, uint16_t id)
+{
+    while (true) {
+        if (o < g.n_walls || o == id) return;
+        if (o < id) {
+            // a lower-index sphere keeps the node if its new ball covers it
+            const int b = o - g.n_walls;
+            if (b < g.nb2) {
+                const double *Bo = g.bodies2 + (size_t)b * kBodyStride;
+                if (body_ok(Bo, g.nx, g.ny, g.nz) && inside(Bo, v.px, v.py, v.pz, g.nx, g.ny, g.nz)) return;
+            }
+        }
+        const uint16_t prev = cas_u16(own + v.n, o, id);
+        if (prev == o) return;
+        o = prev;
     }
 }
 
@@ -134,49 +168,53 @@ __global__ __launch_bounds__(kBlock) void k_walls_init(const uint8_t *wall, uint
     if (n < N) own[n] = wall[n] ? (uint16_t)(wall[n] - 1) : kFluid;
 }
 
-// Old sphere blockIdx.x against its new position (g.bodies2, g.nb2
-// spheres): the nodes it owned and no longer covers take the equilibrium at
-// rho0 and the velocity they had as solids, in the current population
-// buffer, and become fluid (stamp may take them again for another sphere).
+// Workgroups 0 .. nb2 - 1 stamp new sphere b, workgroups nb2 .. nb2 + nb - 1
+// vacate old sphere b - nb2, all in any order.
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_vacate(GeomArgs g)
+__global__ __launch_bounds__(kBlock) void k_geometry(GeomArgs g)
 {
     using St = Store<S>;
-    typename St::T *pop = static_cast<typename St::T *>(g.pop);
-    const int b = blockIdx.x;
-    const double *B = g.bodies + b * kBodyStride;
-    if (!body_ok(B, g.nx, g.ny, g.nz)) return;
-    const double *Bn = g.bodies2 + b * kBodyStride;
-    const bool keeps = b < g.nb2 && body_ok(Bn, g.nx, g.ny, g.nz);
-    const uint16_t id = (uint16_t)(g.n_walls + b);
-    uint16_t *own = g.own;
+    const int tid = threadIdx.x;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
-    // a node the sphere owns lies inside its old ball; one surely inside the
-    // new ball stays owned
-    walk_leaving(B, Bn, keeps, nx, ny, nz, [&](int px, int py, int pz, int n) {
-        if (own[n] != id || (keeps && inside(Bn, px, py, pz, nx, ny, nz))) return;
-        double u0, u1, u2;
-        sphere_velocity(B, px, py, pz, nx, ny, nz, u0, u1, u2);
-        for (int i = 0; i < kQ; ++i) St::st(pop + (size_t)i * g.Ns + n, (float)eq_dev(i, g.rho0, u0, u1, u2));
-        own[n] = kFluid;
-    });
-}
-
-__global__ __launch_bounds__(kBlock) void k_stamp(GeomArgs g)
-{
-    const double *B = g.bodies + blockIdx.x * kBodyStride;
-    if (!body_ok(B, g.nx, g.ny, g.nz)) return;
-    const uint16_t id = (uint16_t)(g.n_walls + blockIdx.x);
     uint16_t *own = g.own;
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
-    // a plain read first: owners only decrease while spheres are stamped, so
-    // a node that reads id or lower needs no atomic (the common case when a
-    // sphere has moved by less than a node)
-    box_chunks(
-        body_box(B, 0), nx, ny, nz, own, [&](const BoxNode &v) { return inside(B, v.px, v.py, v.pz, nx, ny, nz); },
-        [&](const BoxNode &v, uint16_t o) {
-            if (o > id) atomic_min_u16(own + v.n, id);
-        });
+    // stamp: nodes surely inside the new ball (FP32 with a margin that covers
+    // its rounding) skip the exact FP64 test
+    if ((int)blockIdx.x < g.nb2) {
+        const int b = blockIdx.x;
+        const double *B = g.bodies2 + (size_t)b * kBodyStride;
+        if (body_ok(B, nx, ny, nz)) {
+            const uint16_t id = (uint16_t)(g.n_walls + b);
+            const float R2 = (float)(B[9] * B[9]), mg = 0.01f + 1e-5f * R2;
+            const float in2 = R2 - mg, out2 = R2 + mg;
+            box_chunks(
+                body_box(B, 0), nx, ny, nz, own,
+                [&](const BoxNode &v) {
+                    const float dx = foff(v.vx, B[0], nx), dy = foff(v.vy, B[1], ny), dz = foff(v.vz, B[2], nz);
+                    const float d2 = dx * dx + dy * dy + dz * dz;
+                    if (d2 > out2) return false;
+                    return d2 < in2 || inside(B, v.px, v.py, v.pz, nx, ny, nz);
+                },
+                [&](uint16_t o) { return o != id; }, [&](const BoxNode &v, uint16_t o) { stamp_node(g, own, v, o, id); });
+        }
+    } else {
+        // vacate: a node the old sphere owns lies inside its old ball; one
+        // surely inside the new ball stays owned
+        const int b = blockIdx.x - g.nb2;
+        const double *B = g.bodies + (size_t)b * kBodyStride;
+        if (body_ok(B, nx, ny, nz)) {
+            typename St::T *pop = static_cast<typename St::T *>(g.pop);
+            const double *Bn = g.bodies2 + (size_t)b * kBodyStride;
+            const bool keeps = b < g.nb2 && body_ok(Bn, nx, ny, nz);
+            const uint16_t id = (uint16_t)(g.n_walls + b);
+            walk_leaving(B, Bn, keeps, nx, ny, nz, tid & 7, (tid >> 3) & 7, tid >> 6, [&](int px, int py, int pz, int n) {
+                if (own[n] != id || (keeps && inside(Bn, px, py, pz, nx, ny, nz))) return;
+                if (cas_u16(own + n, id, kFluid) != id) return;  // taken by another sphere meanwhile
+                double u0, u1, u2;
+                sphere_velocity(B, px, py, pz, nx, ny, nz, u0, u1, u2);
+                for (int i = 0; i < kQ; ++i) St::st(pop + (size_t)i * g.Ns + n, (float)eq_dev(i, g.rho0, u0, u1, u2));
+            });
+        }
+    }
 }
 
 template <int S>
@@ -299,7 +337,6 @@ __global__ __launch_bounds__(kBlock) void k_count_fluid(const uint16_t *own, int
 }
 
 inline int nblk(long n) { return (int)((n + kBlock - 1) / kBlock); }
-const dim3 kBoxBlock(8, 8, 4);
 
 template <template <int> class K, typename... A>
 hipError_t dispatch(int storage, dim3 grid, dim3 block, hipStream_t s, A... args)
@@ -313,7 +350,7 @@ hipError_t dispatch(int storage, dim3 grid, dim3 block, hipStream_t s, A... args
     return hipGetLastError();
 }
 
-template <int S> struct VacateK { static constexpr auto fn = k_vacate<S>; };
+template <int S> struct GeomK { static constexpr auto fn = k_geometry<S>; };
 template <int S> struct InitK { static constexpr auto fn = k_init_pop<S>; };
 template <int S> struct ExportK { static constexpr auto fn = k_export_pop<S>; };
 template <int S> struct ImportK { static constexpr auto fn = k_import_pop<S>; };
@@ -327,19 +364,12 @@ hipError_t launch_walls_init(const uint8_t *wall, uint16_t *own, int N, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_vacate(int storage, const GeomArgs &g, hipStream_t s)
+hipError_t launch_geometry(int storage, const GeomArgs &g, hipStream_t s)
 {
-    if (g.nb <= 0) return hipSuccess;
-    return dispatch<VacateK>(storage, dim3(g.nb), kBoxBlock, s, g);
+    const int grid = g.nb + g.nb2;
+    if (grid <= 0) return hipSuccess;
+    return dispatch<GeomK>(storage, dim3(grid), dim3(kBlock), s, g);
 }
-
-hipError_t launch_stamp(const GeomArgs &g, hipStream_t s)
-{
-    if (g.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_stamp, dim3(g.nb), dim3(kBlock), 0, s, g);
-    return hipGetLastError();
-}
-
 
 hipError_t launch_init_pop(int storage, const GeomArgs &g, const double *rho, const double *u, hipStream_t s)
 {

@@ -103,6 +103,15 @@ struct LinkArgs {
 constexpr double kFixScale = 4294967296.0;  // 2^32
 constexpr int kWallRep = 64;
 
+// Turn the fixed-point sums into the FP64 forces of the step (spheres, then
+// walls) and clear them for the next step.
+struct FinishArgs {
+    unsigned long long *fsum;
+    int wall_base, nb, n_walls;
+    double *out;                  // [nb + n_walls][6]
+    double *out2;                 // a second copy (the caller's device buffer), or null
+};
+
 // The fused step: per tile, the boundary links of its fluid nodes (the Sec.
 // 2.3 value of every population pulled across a cut link, formed from the
 // current state, and the momentum exchanged on the link), then the pull,
@@ -114,14 +123,7 @@ struct FusedArgs {
     const double *wrec;           // [n_walls][kBodyStride]: each wall as a record {ref, U, 0, 0}
     unsigned long long *fsum;     // fixed-point sums: [max_bodies][6], then [n_walls][kWallRep][6]
     int wall_base;                // max_bodies: first wall copy of fsum
-};
-
-// Turn the fixed-point sums into the FP64 forces of the step (spheres, then
-// walls) and clear them for the next step.
-struct FinishArgs {
-    unsigned long long *fsum;
-    int wall_base, nb, n_walls;
-    double *out;                  // [nb + n_walls][6]
+    FinishArgs fin;               // the previous step's sums (another buffer) to finish first, if fin.fsum
 };
 
 // One lattice of a batch: its fused-step arguments for the batch's tile
@@ -165,9 +167,9 @@ struct GeomArgs {
     int N;
     int Ns;                       // stride between direction arrays
     int n_walls;
-    const double *bodies;
+    const double *bodies;         // the current (old) geometry's table, nb spheres
     int nb;
-    const double *bodies2;        // vacate: the new geometry's table
+    const double *bodies2;        // the new geometry's table, nb2 spheres
     int nb2;
     uint16_t *own;
     void *pop;
@@ -191,8 +193,7 @@ hipError_t launch_adj_links(const AdjLinkArgs &g, hipStream_t s);
 hipError_t launch_adj_reduce(const double *dF_tile, int n_tiles, double *dF, hipStream_t s);
 
 hipError_t launch_walls_init(const uint8_t *wall, uint16_t *own, int N, hipStream_t s);
-hipError_t launch_vacate(int storage, const GeomArgs &g, hipStream_t s);
-hipError_t launch_stamp(const GeomArgs &g, hipStream_t s);
+hipError_t launch_geometry(int storage, const GeomArgs &g, hipStream_t s);
 hipError_t launch_init_pop(int storage, const GeomArgs &g, const double *rho, const double *u,
                            hipStream_t s);
 hipError_t launch_export_pop(int storage, const GeomArgs &g, const double *walls, int dir,
