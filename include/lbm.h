@@ -179,6 +179,25 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *u);
  * (nsteps < 0), HIP, UNSTABLE. */
 lbm_status lbm_step(lbm_handle h, int32_t nsteps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lbm_step
+ * with the fused kernel whatever the step path, whose fixed-point force sums
+ * live in a static device array of the library (2 x LBM_STATIC_FIX_SUMS
+ * 64-bit sums, 1 MiB, held on each device the library runs on until the
+ * process ends) instead of the handle's buffers.  The call allocates
+ * nothing and records no profile events; it clears what it uses of the array
+ * at its start, with a kernel, and turns the sums of its last step into the
+ * forces before it returns, so nothing in the array outlives the call.
+ * Populations and forces are the same bit for bit as lbm_step's.  All calls
+ * on one device share the array: calls that overlap on that device (two
+ * handles on different streams, or threads) race and give wrong forces.
+ * Limit: 6 (n_bodies + 64 n_walls) <= LBM_STATIC_FIX_SUMS, with n_bodies the
+ * larger of the current and the pending sphere count.  Errors: as lbm_step,
+ * CAPACITY beyond the limit, HIP if the array's address could not be found
+ * on the device the handle was created on. */
+#define LBM_STATIC_FIX_SUMS 65536
+lbm_status lbm_step_noalloc(lbm_handle h, int32_t nsteps);
+
 /* Force and torque on every sphere then every wall, of the last step, in
  * FP64 (host arrays of (n_bodies + n_walls) x 3).  Torques of spheres are
  * about their centre, of walls about their reference point.  Synchronises

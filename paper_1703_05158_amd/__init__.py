@@ -21,7 +21,7 @@ __all__ = [
     "LBMError", "LBMConfig", "LBMInfo", "config", "Lattice", "Batch", "TILE_SHAPES", "SphereDrag",
     "lbm_version", "lbm_create", "lbm_destroy", "lbm_last_error", "lbm_set_stream",
     "lbm_set_walls", "lbm_set_bodies", "lbm_set_bodies_device", "lbm_init_fields",
-    "lbm_step", "lbm_get_forces", "lbm_get_forces_device", "lbm_get_populations",
+    "lbm_step", "lbm_step_noalloc", "lbm_get_forces", "lbm_get_forces_device", "lbm_get_populations",
     "lbm_set_populations", "lbm_get_macro", "lbm_get_owner", "lbm_get_state",
     "lbm_set_state", "lbm_get_info", "lbm_count_fluid", "lbm_profile", "lbm_profile_read",
     "lbm_profile_read_parts", "lbm_set_step_path", "lbm_get_step_path",
@@ -76,6 +76,7 @@ _sig = {
     "lbm_set_bodies_device": (ct.c_int, [_H, ct.c_int32, ct.c_void_p]),
     "lbm_init_fields": (ct.c_int, [_H, ct.c_void_p, ct.c_void_p]),
     "lbm_step": (ct.c_int, [_H, ct.c_int32]),
+    "lbm_step_noalloc": (ct.c_int, [_H, ct.c_int32]),
     "lbm_get_forces": (ct.c_int, [_H, ct.c_void_p, ct.c_void_p]),
     "lbm_get_forces_device": (ct.c_int, [_H, ct.c_void_p]),
     "lbm_get_populations": (ct.c_int, [_H, ct.c_void_p]),
@@ -214,6 +215,10 @@ def lbm_init_fields(h, rho=None, u=None) -> None:
 
 def lbm_step(h, nsteps=1) -> None:
     _check(h, _L.lbm_step(h, int(nsteps)))
+
+
+def lbm_step_noalloc(h, nsteps=1) -> None:
+    _check(h, _L.lbm_step_noalloc(h, int(nsteps)))
 
 
 def lbm_get_info(h) -> dict:
@@ -458,6 +463,9 @@ class Lattice:
 
     def step(self, nsteps=1):
         lbm_step(self.h, nsteps)
+
+    def step_noalloc(self, nsteps=1):
+        lbm_step_noalloc(self.h, nsteps)
 
     def get_forces(self):
         return lbm_get_forces(self.h)

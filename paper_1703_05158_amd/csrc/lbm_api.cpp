@@ -48,8 +48,10 @@ struct lbm_ctx {
     // turns them into acc.
     unsigned long long *fsum[2] = {nullptr, nullptr};
     int fcur = 0;                      // buffer of the next fused step
-    bool fpending = false;             // fsum[fcur ^ 1] holds the last step's sums, not yet in acc
-    int fpend_nb = 0, fpend_nw = 0;    // their body and wall counts
+    bool fpending = false;             // the last step's sums are not yet in acc
+    FinishArgs pend{};                 // where they are: buffer, wall base, counts
+    unsigned long long *static_fix = nullptr; // this device's static sums of lbm_step_noalloc
+    hipError_t static_fix_err = hipSuccess;   // why static_fix is null
     int path = LBM_PATH_FUSED;         // lbm_step_path
     uint64_t geom_gen = 0;             // bumped whenever the geometry, the body force or the state is replaced
     int tile = kTile64x2x2;            // TileShape of the step kernel
@@ -253,12 +255,9 @@ FusedArgs fused_args(const lbm_ctx *h)
 // The pending sums of the last fused step, to be turned into acc.
 FinishArgs pending_finish(const lbm_ctx *h)
 {
-    FinishArgs fa{};
-    fa.fsum = h->fsum[h->fcur ^ 1];
-    fa.wall_base = h->cfg.max_bodies;
-    fa.nb = h->fpend_nb;
-    fa.n_walls = h->fpend_nw;
+    FinishArgs fa = h->pend;
     fa.out = h->acc;
+    fa.out2 = nullptr;
     return fa;
 }
 
@@ -543,6 +542,7 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
     if (!h) return LBM_ERR_OOM;
     h->cfg = c;
     h->stream = (hipStream_t)c.stream;
+    h->static_fix_err = static_fix_scratch(&h->static_fix);  // on the current device, once per device
     h->N = (int)N;
     h->Ns = pop_stride(h->N);
     h->sbytes = c.storage == 0 ? 4 : 2;
@@ -784,8 +784,10 @@ namespace {
 // One step of the handle: inflow-plane update, re-rasterisation when the
 // bodies changed, then the fused step kernel (which also finishes the force
 // sums of the step before, if nothing read them), or (the split path) the
-// boundary-link pass and the pull-collide kernel.
-lbm_status step_once(lbm_ctx *h)
+// boundary-link pass and the pull-collide kernel.  With fix, the fused kernel
+// runs whatever the path, its force sums going to fix (bodies first, then the
+// wall copies right after them) instead of the handle's buffers.
+lbm_status step_once(lbm_ctx *h, unsigned long long *fix = nullptr)
 {
     const lbm_config &c = h->cfg;
     std::array<hipEvent_t, 4> ev{};
@@ -795,19 +797,22 @@ lbm_status step_once(lbm_ctx *h)
     if (h->zieb_z >= 0) HIP_TRY(h, launch_zieb_update(c.storage, zieb_args(h), h->stream));
     if (h->dirty) TRY(rasterize_update(h));
     if (h->prof) HIP_TRY(h, prof_mark(h, &ev[1]));
-    if (h->path == LBM_PATH_FUSED) {
+    if (fix || h->path == LBM_PATH_FUSED) {
         ev[2] = ev[1];
         FusedArgs f = fused_args(h);
+        if (fix) {
+            f.fsum = fix;
+            f.wall_base = h->nb_state;
+        }
         if (h->fpending) {  // the last step's forces, unread: into acc by this launch
             f.fin = pending_finish(h);
             h->fpending = false;
         }
         HIP_TRY(h, launch_fused(c.storage, f, h->stream));
         if (h->prof) HIP_TRY(h, prof_mark(h, &ev[3]));
-        h->fpend_nb = h->nb_state;
-        h->fpend_nw = h->n_walls;
+        h->pend = FinishArgs{f.fsum, f.wall_base, h->nb_state, h->n_walls, h->acc, nullptr};
         h->fpending = true;
-        h->fcur ^= 1;
+        if (!fix) h->fcur ^= 1;
     } else {
         TRY(finish_forces(h, nullptr));
         LinkArgs la = link_args(h);
@@ -851,6 +856,47 @@ lbm_status lbm_step(lbm_handle h, int32_t nsteps)
         }
     }
     return LBM_OK;
+}
+
+static_assert(kStaticFixHalf == LBM_STATIC_FIX_SUMS && kWallRep == 64, "static force scratch as documented");
+
+lbm_status lbm_step_noalloc(lbm_handle h, int32_t nsteps)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (nsteps < 0) return fail(h, LBM_ERR_ARG, "nsteps < 0");
+    lbm_status st = check_ready(h);
+    if (st != LBM_OK) return st;
+    if (!h->static_fix)
+        return fail(h, LBM_ERR_HIP, "static force scratch unavailable: %s", hipGetErrorString(h->static_fix_err));
+    const int nb = std::max(h->nb_state, h->dirty ? h->nb_next : 0);
+    const size_t need = 6 * ((size_t)nb + (size_t)h->n_walls * kWallRep);
+    if (need > (size_t)kStaticFixHalf)
+        return fail(h, LBM_ERR_CAPACITY,
+                    "%d bodies and %d walls need %zu fixed-point sums per step; the static scratch holds %d",
+                    nb, h->n_walls, need, kStaticFixHalf);
+    if (nsteps == 0) return LBM_OK;
+    const lbm_config &c = h->cfg;
+    // the halves start at zero (a previous call may have stopped early);
+    // cleared by a kernel, not a memset node, should the call be captured
+    HIP_TRY(h, launch_zero_fix(h->static_fix, kStaticFixHalf + (int)need, h->stream));
+    const bool prof = h->prof;
+    h->prof = false;  // no events: the profile pool may grow
+    st = LBM_OK;
+    for (int s = 0; s < nsteps && st == LBM_OK; ++s) {
+        st = step_once(h, h->static_fix + (size_t)(s & 1) * kStaticFixHalf);
+        if (st == LBM_OK && c.nan_guard_every > 0 && (h->steps_done % c.nan_guard_every == 0 || s == nsteps - 1)) {
+            hipError_t e = hipMemcpyAsync(h->flag_host, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess)
+                st = fail(h, LBM_ERR_HIP, "%s", hipGetErrorString(e));
+            else if (*h->flag_host)
+                st = fail(h, LBM_ERR_UNSTABLE, "non-finite or non-positive density/velocity by step %d", h->steps_done);
+        }
+    }
+    h->prof = prof;
+    // nothing may stay pending in the shared array when the call returns
+    const lbm_status fst = finish_forces(h, nullptr);
+    return st != LBM_OK ? st : fst;
 }
 
 lbm_status lbm_get_forces(lbm_handle h, double *F, double *T)

@@ -33,6 +33,9 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <map>
+#include <mutex>
+
 namespace lbm {
 namespace {
 
@@ -463,6 +466,29 @@ hipError_t launch_zero_fix(unsigned long long *p, int n, hipStream_t s)
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero_fix, dim3(nblk(n)), dim3(kBlock), 0, s, p, n);
     return hipGetLastError();
+}
+
+// The device array behind lbm_step_noalloc's force sums.  Host code takes
+// its address per device from static_fix_scratch and never uses the name.
+static __device__ __align__(256) unsigned long long scratch[2 * kStaticFixHalf];
+
+hipError_t static_fix_scratch(unsigned long long **out)
+{
+    static std::mutex mu;
+    static std::map<int, unsigned long long *> addr;  // device -> address of scratch there
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        it = addr.emplace(dev, static_cast<unsigned long long *>(p)).first;
+    }
+    *out = it->second;
+    return hipSuccess;
 }
 
 int batch_step_blocks_per_cu(int storage, int shape)

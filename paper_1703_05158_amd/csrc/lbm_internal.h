@@ -182,6 +182,13 @@ hipError_t launch_links(int storage, const LinkArgs &a, hipStream_t s);
 hipError_t launch_fused(int storage, const FusedArgs &f, hipStream_t s);
 hipError_t launch_finish(const FinishArgs &fa, hipStream_t s);
 hipError_t launch_zero_fix(unsigned long long *p, int n, hipStream_t s);
+
+// Fixed-point force sums of lbm_step_noalloc: a file-scope device array of
+// two halves of kStaticFixHalf entries (1 MiB in all), shared by every call
+// on a device.  static_fix_scratch gives its address on the current device
+// (looked up once per device).
+constexpr int kStaticFixHalf = 65536;
+hipError_t static_fix_scratch(unsigned long long **out);
 hipError_t launch_batch_step(int storage, int shape, const BatchStepArgs &b, int grid, hipStream_t s);
 int batch_step_blocks_per_cu(int storage, int shape);   // resident workgroups per CU of the persistent step kernel
 hipError_t launch_batch_finish(const BatchStepArgs &b, hipStream_t s);
