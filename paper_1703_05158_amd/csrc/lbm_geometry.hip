@@ -1,7 +1,7 @@
 // Owner-map maintenance and state import/export kernels (gfx950).
 //
 // The owner map is kept incrementally when spheres move, in one launch with
-// one workgroup per new sphere and one per old sphere, in any order:
+// one wavefront per new sphere and one per old sphere, in any order:
 //  - stamp: sphere c takes every node of its new ball unless a wall or a
 //    lower-index sphere whose new ball also covers it owns the node; it takes
 //    the node by compare-and-swap from any other owner (a higher index, the
@@ -27,104 +27,11 @@ namespace {
 
 using namespace dev;
 
-// Offset of box coordinate v from centre coordinate c, folded to the
-// nearest periodic image in FP64 and then rounded once to FP32, so that its
-// rounding error is relative to the folded offset (at most half an FP32 ulp
-// of the ball's radius plus one), not to the box size.
-__device__ __forceinline__ float foff(int v, double c, int n) { return (float)min_image((double)v - c, n); }
-
-// The nodes of old ball B's box with the (8, 8, 4) workgroup, skipping those
-// surely outside B and, when keeps, those surely inside the new ball Bn:
-// FP32 offsets with a margin that covers their rounding (the exact FP64
-// tests are left to f, which sees every node either test could accept).
-template <typename F>
-__device__ __forceinline__ void walk_leaving(const double *B, const double *Bn, bool keeps, int nx, int ny, int nz,
-                                             int tx, int ty, int tz, F &&f)
-{
-    const Box bx = body_box(B, 0);
-    const float R2 = (float)(B[9] * B[9]);
-    const float out2 = R2 + 0.01f + 1e-5f * R2;
-    const float Rn2 = keeps ? (float)(Bn[9] * Bn[9]) : 0.0f;
-    const float in2 = keeps ? Rn2 - (0.01f + 1e-5f * Rn2) : -1.0f;
-    const double cx = keeps ? Bn[0] : 0.0, cy = keeps ? Bn[1] : 0.0, cz = keeps ? Bn[2] : 0.0;
-    for (int kz = tz; kz < bx.ez; kz += 4) {
-        const int vz = bx.z0 + kz, pz = wrap1(vz, nz);
-        const float dz = foff(vz, B[2], nz), ez = foff(vz, cz, nz);
-        for (int ky = ty; ky < bx.ey; ky += 8) {
-            const int vy = bx.y0 + ky, py = wrap1(vy, ny);
-            const float dy = foff(vy, B[1], ny), ey = foff(vy, cy, ny);
-            const float dyz = dy * dy + dz * dz, eyz = ey * ey + ez * ez;
-            for (int kx = tx; kx < bx.ex; kx += 8) {
-                const int vx = bx.x0 + kx;
-                const float dx = foff(vx, B[0], nx);
-                if (dx * dx + dyz > out2) continue;
-                if (keeps) {
-                    const float ex = foff(vx, cx, nx);
-                    if (ex * ex + eyz < in2) continue;
-                }
-                const int px = wrap1(vx, nx);
-                f(px, py, pz, px + nx * (py + ny * pz));
-            }
-        }
-    }
-}
-
-constexpr int kBoxU = 8;  // box nodes per thread whose owner loads are in flight together
-
-// Node k (x fastest) of a body's box: its coordinates and index.
-struct BoxNode {
-    int vx, vy, vz;   // unwrapped
+// A node of the lattice: wrapped coordinates and index.
+struct Node {
     int px, py, pz;
     uint32_t n;
 };
-
-__device__ __forceinline__ BoxNode box_node(const Box &bx, int k, int nx, int ny, int nz)
-{
-    const int kx = k % bx.ex, r = k / bx.ex;
-    BoxNode v;
-    v.vx = bx.x0 + kx;
-    v.vy = bx.y0 + r % bx.ey;
-    v.vz = bx.z0 + r / bx.ey;
-    v.px = wrap1(v.vx, nx);
-    v.py = wrap1(v.vy, ny);
-    v.pz = wrap1(v.vz, nz);
-    v.n = (uint32_t)(v.px + nx * (v.py + ny * v.pz));
-    return v;
-}
-
-// The nodes of a body's box in chunks of kBoxU per thread (a 1-D
-// workgroup): the owner codes of a chunk are loaded together (keep(node)
-// selects the nodes to load), then act(node, owner) runs on each loaded node
-// whose owner passes want(owner).  Only the box index k and the node index
-// are held across the loads; the coordinates are made again for act.
-template <typename Keep, typename Want, typename Act>
-__device__ __forceinline__ void box_chunks(const Box &bx, int nx, int ny, int nz, const uint16_t *own, Keep &&keep,
-                                           Want &&want, Act &&act)
-{
-    const int total = bx.ex * bx.ey * bx.ez;
-    for (int base = 0; base < total; base += kBoxU * kBlock) {
-        uint32_t n[kBoxU];
-        uint16_t o[kBoxU];
-        unsigned ld = 0;
-#pragma unroll
-        for (int u = 0; u < kBoxU; ++u) {
-            const int k = base + u * kBlock + (int)threadIdx.x;
-            o[u] = 0;
-            n[u] = 0;
-            if (k < total) {
-                const BoxNode v = box_node(bx, k, nx, ny, nz);
-                if (keep(v)) {
-                    ld |= 1u << u;
-                    n[u] = v.n;
-                    o[u] = own[v.n];
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kBoxU; ++u)
-            if (((ld >> u) & 1u) && want(o[u])) act(box_node(bx, base + u * kBlock + (int)threadIdx.x, nx, ny, nz), o[u]);
-    }
-}
 
 // Compare-and-swap of a 16-bit owner code (through its 32-bit word): the
 // code found (expect on success).
@@ -144,7 +51,7 @@ __device__ __forceinline__ uint16_t cas_u16(uint16_t *addr, uint16_t expect, uin
 }
 
 // Sphere `id` (new geometry) takes node v, found with owner o.
-__device__ __forceinline__ void stamp_node(const GeomArgs &g, uint16_t *own, const BoxNode &v, uint16_t o, uint16_t id)
+__device__ __forceinline__ void stamp_node(const GeomArgs &g, uint16_t *own, const Node &v, uint16_t o, uint16_t id)
 {
     while (true) {
         if (o < g.n_walls || o == id) return;
@@ -162,58 +69,246 @@ __device__ __forceinline__ void stamp_node(const GeomArgs &g, uint16_t *own, con
     }
 }
 
+// The nodes of ball B in the column (px, py) of the lattice: the unwrapped z
+// range [lo, hi] (empty when lo > hi), exactly those for which inside() holds.
+// The range is [Z - h, Z + h] with h^2 = R^2 - (dx^2 + dy^2).  A first pass
+// in FP32 takes the offsets from the box origin (kx - ox for the column at
+// box position kx; |offsets| <= R + 1) and bounds h^2 within +-eps2, an upper
+// bound of its FP32 error with a wide margin; where both bounds give the same
+// end nodes those are the ends of the exact range (the FP64 test of inside()
+// differs from the exact one only within about 1e-13 of the surface).
+// Otherwise the FP64 pass decides: dx^2 + dy^2 formed as inside() forms it
+// and FP64 h settle every node farther than 1e-6 from both ends (their
+// roundings move an end by about 2^-52 R^2 / h < 1e-7 while h > max(1e-4,
+// 1e-8 R^2)), and inside() itself decides the rest: along a column |p - X|^2
+// grows with |z - Z| (each rounding is monotone), so the nodes inside form
+// one range.
+struct BallCols {
+    float ox, oy, oz;  // centre minus box origin, per axis
+    float r2, eps2;    // R^2 and the error bound of h^2
+    float m;           // bound of the error of a range end, with margin
+};
+
+__device__ __forceinline__ BallCols ball_cols(const double *B, const Box &bx)
+{
+    BallCols bc;
+    bc.ox = (float)(B[0] - (double)bx.x0);
+    bc.oy = (float)(B[1] - (double)bx.y0);
+    bc.oz = (float)(B[2] - (double)bx.z0);
+    bc.r2 = (float)(B[9] * B[9]);
+    // the FP32 error of h^2 stays below 1e-6 (R + 1)^2 and that of an end
+    // (the offset oz, the sums, the square root) below 1e-6 (R + 1): the
+    // bounds below are ten times these
+    bc.eps2 = 1e-5f * (bc.r2 + 1.0f) + 2e-5f * (float)B[9];
+    bc.m = 1e-5f * ((float)B[9] + 1.0f);
+    return bc;
+}
+
+__device__ __forceinline__ void column_range(const double *B, const Box &bx, const BallCols &bc, int kx, int ky,
+                                             int px, int py, int nx, int ny, int nz, int &lo, int &hi)
+{
+#pragma clang fp contract(off)
+    lo = 1;
+    hi = 0;
+    {
+        const float dx = (float)kx - bc.ox, dy = (float)ky - bc.oy;
+        const float h2 = bc.r2 - (dx * dx + dy * dy);
+        if (h2 < -bc.eps2) return;  // no node of the column within R
+        if (h2 > bc.eps2) {
+            const float hl = __builtin_sqrtf(h2 - bc.eps2), hh = __builtin_sqrtf(h2 + bc.eps2);
+            const float m = bc.m;
+            // an end settled this way lies at least m / 2 from every node
+            const int l0 = (int)ceilf(bc.oz - hh - m), l1 = (int)ceilf(bc.oz - hl + m);
+            const int h0 = (int)floorf(bc.oz + hl - m), h1 = (int)floorf(bc.oz + hh + m);
+            if (l0 == l1 && h0 == h1) {
+                lo = bx.z0 + l0;
+                hi = bx.z0 + h0;
+                return;
+            }
+        }
+    }
+    const double r2 = B[9] * B[9];
+    const double dx = min_image((double)px - B[0], nx);
+    const double dy = min_image((double)py - B[1], ny);
+    const double sxy = dx * dx + dy * dy;
+    if (sxy > r2) return;  // |p - X|^2 >= sxy for every node of the column
+    const double h = sqrt(r2 - sxy);
+    const double za = B[2] - h, zb = B[2] + h;
+    const double fa = floor(za), fb = floor(zb);
+    lo = (int)fa + 1;
+    hi = (int)fb;
+    constexpr double kSure = 1e-6;
+    if (h > 1e-4 && h > 1e-8 * r2 && za - fa > kSure && fa + 1.0 - za > kSure && zb - fb > kSure && fb + 1.0 - zb > kSure)
+        return;
+    const int zmin = (int)ceil(B[2] - B[9]), zmax = (int)floor(B[2] + B[9]);  // the ball's box
+    lo = max(lo - 2, zmin);
+    hi = min(hi + 1, zmax);
+    while (lo <= hi && !inside(B, px, py, wrap1(lo, nz), nx, ny, nz)) ++lo;
+    while (hi >= lo && !inside(B, px, py, wrap1(hi, nz), nx, ny, nz)) --hi;
+}
+
+constexpr int kColU = 8;         // nodes of a lane whose owner loads are in flight together
+constexpr int kColsPerLane = 4;  // columns of a stamp lane whose nodes are taken together
+
 __global__ __launch_bounds__(kBlock) void k_walls_init(const uint8_t *wall, uint16_t *own, int N)
 {
     const int n = blockIdx.x * kBlock + threadIdx.x;
     if (n < N) own[n] = wall[n] ? (uint16_t)(wall[n] - 1) : kFluid;
 }
 
-// Workgroups 0 .. nb2 - 1 stamp new sphere b, workgroups nb2 .. nb2 + nb - 1
-// vacate old sphere b - nb2, all in any order.
+// Lattice coordinates of node index n (a rare path: integer divisions).
+__device__ __forceinline__ Node node_of(uint32_t n, int nx, int ny)
+{
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny, r = n % plane;
+    return Node{(int)(r % (uint32_t)nx), (int)(r / (uint32_t)nx), (int)(n / plane), n};
+}
+
+// One wavefront per job: jobs 0 .. nb2 - 1 stamp new sphere b, jobs nb2 ..
+// nb2 + nb - 1 vacate old sphere b, all in any order.  The lanes take the
+// (x, y) columns of the sphere's box, kColsPerLane at a time; each column's
+// range of ball nodes comes from column_range, and the owner codes of a
+// lane's nodes are loaded kColU at a time across its columns, so that a job
+// waits for few memory round trips.
 template <int S>
 __global__ __launch_bounds__(kBlock) void k_geometry(GeomArgs g)
 {
     using St = Store<S>;
-    const int tid = threadIdx.x;
+    __shared__ uint32_t cand[kColU][kBlock];  // vacate: a lane's leaving nodes, flushed kColU at a time
+    // the job is the same on every lane of the wavefront: made uniform, so that
+    // its sphere records are scalar loads
+    const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6));
+    if (w >= g.nb + g.nb2) return;
+    // stamp and vacate jobs alternate while both last (the two kinds cost
+    // differently); job < nb2 stamps sphere job, else vacates job - nb2
+    const int mb = min(g.nb, g.nb2);
+    const int job = w < 2 * mb ? ((w & 1) ? g.nb2 + (w >> 1) : (w >> 1))
+                               : (g.nb2 > g.nb ? w - mb : g.nb2 + (w - mb));
+    const int lane = threadIdx.x & 63, tid = threadIdx.x;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     uint16_t *own = g.own;
-    // stamp: nodes surely inside the new ball (FP32 with a margin that covers
-    // its rounding) skip the exact FP64 test
-    if ((int)blockIdx.x < g.nb2) {
-        const int b = blockIdx.x;
-        const double *B = g.bodies2 + (size_t)b * kBodyStride;
-        if (body_ok(B, nx, ny, nz)) {
-            const uint16_t id = (uint16_t)(g.n_walls + b);
-            const float R2 = (float)(B[9] * B[9]), mg = 0.01f + 1e-5f * R2;
-            const float in2 = R2 - mg, out2 = R2 + mg;
-            box_chunks(
-                body_box(B, 0), nx, ny, nz, own,
-                [&](const BoxNode &v) {
-                    const float dx = foff(v.vx, B[0], nx), dy = foff(v.vy, B[1], ny), dz = foff(v.vz, B[2], nz);
-                    const float d2 = dx * dx + dy * dy + dz * dz;
-                    if (d2 > out2) return false;
-                    return d2 < in2 || inside(B, v.px, v.py, v.pz, nx, ny, nz);
-                },
-                [&](uint16_t o) { return o != id; }, [&](const BoxNode &v, uint16_t o) { stamp_node(g, own, v, o, id); });
+    if (job < g.nb2) {
+        // stamp: every node of the new ball not yet owned by the sphere
+        const double *B = g.bodies2 + (size_t)job * kBodyStride;
+        if (!body_ok(B, nx, ny, nz)) return;
+        const uint16_t id = (uint16_t)(g.n_walls + job);
+        const Box bx = body_box(B, 0);
+        const BallCols bc = ball_cols(B, bx);
+        const int ncols = bx.ex * bx.ey;
+        for (int cb = 0; cb < ncols; cb += 64 * kColsPerLane) {
+            // the lane's columns: first z, node count, column index
+            int lo[kColsPerLane], cum[kColsPerLane + 1];
+            uint32_t cx[kColsPerLane];
+            cum[0] = 0;
+#pragma unroll
+            for (int j = 0; j < kColsPerLane; ++j) {
+                const int c = cb + j * 64 + lane;
+                int l = 1, h = 0;
+                cx[j] = 0;
+                if (c < ncols) {
+                    const int ky = c / bx.ex, kx = c - ky * bx.ex;
+                    const int px = wrap1(bx.x0 + kx, nx), py = wrap1(bx.y0 + ky, ny);
+                    column_range(B, bx, bc, kx, ky, px, py, nx, ny, nz, l, h);
+                    cx[j] = (uint32_t)(px + nx * py);
+                }
+                lo[j] = l;
+                cum[j + 1] = cum[j] + max(h - l + 1, 0);
+            }
+            // the lane's nodes k = 0 .. cum[kColsPerLane] - 1, column by column
+            for (int k0 = 0; k0 < cum[kColsPerLane]; k0 += kColU) {
+                uint32_t nn[kColU];
+                unsigned todo = 0;
+#pragma unroll
+                for (int u = 0; u < kColU; ++u) {
+                    const int k = k0 + u;
+                    int z = lo[0] + k;
+                    uint32_t col = cx[0];
+#pragma unroll
+                    for (int j = 1; j < kColsPerLane; ++j)
+                        if (k >= cum[j]) {
+                            z = lo[j] + (k - cum[j]);
+                            col = cx[j];
+                        }
+                    nn[u] = col + plane * (uint32_t)wrap1(z, nz);
+                    if (k < cum[kColsPerLane] && own[nn[u]] != id) todo |= 1u << u;
+                }
+                // the nodes not yet the sphere's (few: most were already)
+                while (todo) {
+                    const int u = __builtin_ctz(todo);
+                    todo &= todo - 1;
+                    uint32_t n = nn[0];
+#pragma unroll
+                    for (int v = 1; v < kColU; ++v)
+                        if (u == v) n = nn[v];
+                    stamp_node(g, own, node_of(n, nx, ny), own[n], id);
+                }
+            }
         }
-    } else {
-        // vacate: a node the old sphere owns lies inside its old ball; one
-        // surely inside the new ball stays owned
-        const int b = blockIdx.x - g.nb2;
+    } else if (job < g.nb2 + g.nb) {
+        // vacate: nodes of the old ball outside the new one that the sphere
+        // still owns turn fluid (unless another sphere takes them first) and
+        // are refilled
+        const int b = job - g.nb2;
         const double *B = g.bodies + (size_t)b * kBodyStride;
-        if (body_ok(B, nx, ny, nz)) {
-            typename St::T *pop = static_cast<typename St::T *>(g.pop);
-            const double *Bn = g.bodies2 + (size_t)b * kBodyStride;
-            const bool keeps = b < g.nb2 && body_ok(Bn, nx, ny, nz);
-            const uint16_t id = (uint16_t)(g.n_walls + b);
-            walk_leaving(B, Bn, keeps, nx, ny, nz, tid & 7, (tid >> 3) & 7, tid >> 6, [&](int px, int py, int pz, int n) {
-                if (own[n] != id || (keeps && inside(Bn, px, py, pz, nx, ny, nz))) return;
-                if (cas_u16(own + n, id, kFluid) != id) return;  // taken by another sphere meanwhile
+        if (!body_ok(B, nx, ny, nz)) return;
+        typename St::T *pop = static_cast<typename St::T *>(g.pop);
+        const double *Bn = g.bodies2 + (size_t)b * kBodyStride;
+        const bool keeps = b < g.nb2 && body_ok(Bn, nx, ny, nz);
+        const uint16_t id = (uint16_t)(g.n_walls + b);
+        const Box bx = body_box(B, 0);
+        int cnt = 0;
+        auto flush = [&]() {
+            uint32_t nn[kColU];
+            uint16_t o[kColU];
+#pragma unroll
+            for (int u = 0; u < kColU; ++u) {
+                nn[u] = u < cnt ? cand[u][tid] : 0u;
+                o[u] = u < cnt ? own[nn[u]] : (uint16_t)0;
+            }
+#pragma unroll
+            for (int u = 0; u < kColU; ++u) {
+                if (u >= cnt || o[u] != id || cas_u16(own + nn[u], id, kFluid) != id) continue;
+                const Node v = node_of(nn[u], nx, ny);
                 double u0, u1, u2;
-                sphere_velocity(B, px, py, pz, nx, ny, nz, u0, u1, u2);
-                for (int i = 0; i < kQ; ++i) St::st(pop + (size_t)i * g.Ns + n, (float)eq_dev(i, g.rho0, u0, u1, u2));
-            });
+                sphere_velocity(B, v.px, v.py, v.pz, nx, ny, nz, u0, u1, u2);
+                for (int i = 0; i < kQ; ++i)
+                    St::st(pop + (size_t)i * g.Ns + v.n, (float)eq_dev(i, g.rho0, u0, u1, u2));
+            }
+            cnt = 0;
+        };
+        const BallCols bc = ball_cols(B, bx);
+        Box bxn{};
+        BallCols bcn{};
+        if (keeps) {
+            bxn = body_box(Bn, 0);
+            bcn = ball_cols(Bn, bxn);
         }
+        for (int c = lane; c < bx.ex * bx.ey; c += 64) {
+            const int ky = c / bx.ex, kx = c - ky * bx.ex;
+            const int px = wrap1(bx.x0 + kx, nx), py = wrap1(bx.y0 + ky, ny);
+            int lo, hi, nlo = 1, nhi = 0;
+            column_range(B, bx, bc, kx, ky, px, py, nx, ny, nz, lo, hi);
+            if (lo > hi) continue;
+            if (keeps) {
+                // the column's position in the new ball's box (the image nearest its origin)
+                int kxn = px - bxn.x0, kyn = py - bxn.y0;
+                if (kxn < 0) kxn += nx; else if (kxn >= nx) kxn -= nx;
+                if (kyn < 0) kyn += ny; else if (kyn >= ny) kyn -= ny;
+                if (kxn < bxn.ex && kyn < bxn.ey) column_range(Bn, bxn, bcn, kxn, kyn, px, py, nx, ny, nz, nlo, nhi);
+            }
+            // the new range as a periodic interval of wrapped z: start ns, length nlen
+            const int ns = wrap1(nlo, nz), nlen = max(nhi - nlo + 1, 0);
+            const uint32_t col = (uint32_t)(px + nx * py);
+            for (int vz = lo; vz <= hi; ++vz) {
+                const int pz = wrap1(vz, nz);
+                int d = pz - ns;
+                if (d < 0) d += nz;
+                if (d < nlen) continue;  // stays in the ball
+                cand[cnt][tid] = col + plane * (uint32_t)pz;
+                if (++cnt == kColU) flush();
+            }
+        }
+        if (cnt) flush();
     }
 }
 
@@ -366,8 +461,9 @@ hipError_t launch_walls_init(const uint8_t *wall, uint16_t *own, int N, hipStrea
 
 hipError_t launch_geometry(int storage, const GeomArgs &g, hipStream_t s)
 {
-    const int grid = g.nb + g.nb2;
-    if (grid <= 0) return hipSuccess;
+    const int jobs = g.nb + g.nb2;
+    if (jobs <= 0) return hipSuccess;
+    const int grid = (jobs + kBlock / 64 - 1) / (kBlock / 64);
     return dispatch<GeomK>(storage, dim3(grid), dim3(kBlock), s, g);
 }
 
