@@ -50,9 +50,12 @@ __device__ __forceinline__ void zieb_plane(const StepArgs &a, const typename Sto
 }
 
 // Collide the streamed deviations g of node idx and store the result into
-// dst.  Every lane of the wavefront stores (a solid lane stores zeros): a
-// store with lanes switched off writes partial 128-byte lines, which cost a
-// read-modify-write in HBM.  `fluid` selects the lanes whose values count.
+// dst.  Every lane of the wavefront stores: a store with lanes switched off
+// writes partial 128-byte lines, which cost a read-modify-write in HBM.  A
+// solid lane (g = 0) stores the collision of the rest state, a finite value
+// that nothing reads (a solid node's populations are never pulled, and a
+// node that turns fluid is refilled).  `fluid` selects the lanes whose
+// values count.
 template <int S>
 __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g)[kQ], bool fluid, uint32_t idx,
                                               typename Store<S>::T *__restrict__ dst)
@@ -126,7 +129,7 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g
     const float a1 = w1 * A, a2 = w2 * A, b1 = w1 * B, b2 = w2 * B, d1 = w1 * D, d2 = w2 * D;
     const float e1 = 9.0f * w1 * cf, e2 = 9.0f * w2 * cf;   // times c.F: the source's cu term
     const float o1 = 3.0f * w1 * cf, o2 = 3.0f * w2 * cf;   // times c.F: the source's odd term
-    St::stnt(at(dst, idx), fluid ? om1 * g[0] + (float)wgt(0) * A : 0.0f);
+    St::stnt(at(dst, idx), om1 * g[0] + (float)wgt(0) * A);
 #pragma unroll
     for (int i = 1; i <= 9; ++i) {
         const bool axis = wgt(i) == wgt(1);
@@ -135,8 +138,8 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g
         const float ev = (axis ? a1 : a2) + cu * ((axis ? b1 : b2) * cu + (axis ? e1 : e2) * cF);
         const float od = (axis ? d1 : d2) * cu + (axis ? o1 : o2) * cF;
         const float vp = om1 * g[i] + (ev + od), vm = om1 * g[i + 9] + (ev - od);
-        St::stnt(at(dst + (size_t)i * Ns, idx), fluid ? vp : 0.0f);
-        St::stnt(at(dst + (size_t)(i + 9) * Ns, idx), fluid ? vm : 0.0f);
+        St::stnt(at(dst + (size_t)i * Ns, idx), vp);
+        St::stnt(at(dst + (size_t)(i + 9) * Ns, idx), vm);
     }
 }
 

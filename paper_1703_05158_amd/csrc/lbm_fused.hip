@@ -175,10 +175,17 @@ __device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds &lds, in
     const float vr = St::round(link_value(g.q, fk, fa, fb, behind, g.mw));
     lds.val[I - 1][nl] = vr;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    link_force(link_momentum(fk, vr, I, a.rho0), I, g, acc);
+    const double mom = link_momentum(fk, vr, I, a.rho0);
+    link_force(mom, I, g, acc);
     unsigned long long v[6];
+    // F = -mom c_I: its fixed-point components are -c M with M = fix(mom)
+    // (the rounding is odd-symmetric)
+    const unsigned long long M = to_fix(mom);
+    const int cI[3] = {dcx(I), dcy(I), dcz(I)};
 #pragma unroll
-    for (int c = 0; c < 6; ++c) v[c] = to_fix(acc[c]);
+    for (int c = 0; c < 3; ++c) v[c] = cI[c] > 0 ? 0ull - M : (cI[c] < 0 ? M : 0ull);
+#pragma unroll
+    for (int c = 3; c < 6; ++c) v[c] = to_fix(acc[c]);
     table_add(f, lds, os, v, t);
 }
 

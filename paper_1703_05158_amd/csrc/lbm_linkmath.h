@@ -109,13 +109,13 @@ __device__ __forceinline__ double link_momentum(float fk, float vr, int I, float
 }
 
 // Force mom c_K on the body and its torque about the lever arm
-// x_b - X = d - q c_I, added to acc[6] = {F, T} (FP64).
+// x_b - X = d - q c_I, added to acc[6] = {F, T} (FP64).  The force is
+// parallel to c_I, so (d - q c_I) x F = d x F: the arm is taken as d.
 __device__ __forceinline__ void link_force(double mom, int I, const LinkGeo &l, double (&acc)[6])
 {
 #pragma clang fp contract(off)
     const int cx = dcx(I), cy = dcy(I), cz = dcz(I);
-    const double qd = (double)l.q;
-    const double a0 = l.d0 - qd * cx, a1 = l.d1 - qd * cy, a2 = l.d2 - qd * cz;
+    const double a0 = l.d0, a1 = l.d1, a2 = l.d2;
     const double F0 = -mom * cx, F1 = -mom * cy, F2 = -mom * cz;
     acc[0] += F0;
     acc[1] += F1;
@@ -125,21 +125,23 @@ __device__ __forceinline__ void link_force(double mom, int I, const LinkGeo &l, 
     acc[5] += a0 * F1 - a1 * F0;
 }
 
-// Exclusive prefix of `cnt` over the workgroup and the total (wtot: one int
-// per wavefront in LDS).  Contains a barrier.
+// Exclusive prefix of `cnt` (0 <= cnt < 64) over the workgroup and the total
+// (wtot: one int per wavefront in LDS).  Contains a barrier.
 __device__ __forceinline__ int block_scan(int cnt, int *wtot, int &tot)
 {
     constexpr int kWaves = kBlock / 64;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int incl = cnt;
+    // the wavefront's prefix bit plane by bit plane (cnt < 64): the lanes
+    // below this one with bit b set, from a ballot
+    int pos = 0, wsum = 0;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int v = __shfl_up(incl, off);
-        if (lane >= off) incl += v;
+    for (int b = 0; b < 6; ++b) {
+        const unsigned long long m = __ballot((cnt >> b) & 1);
+        pos += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << b;
+        wsum += __popcll(m) << b;
     }
-    if (lane == 63) wtot[wv] = incl;
+    if (lane == 0) wtot[wv] = wsum;
     __syncthreads();
-    int pos = incl - cnt;
     tot = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) {
