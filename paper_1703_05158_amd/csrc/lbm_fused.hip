@@ -46,8 +46,10 @@ constexpr int kRec = 16;        // bodies of a tile with a slot in the LDS force
 constexpr int kCopies = 4;      // copies of the table's sums (by lane), so fewer lanes add to one address
 
 struct FusedLds {
-    uint32_t item[kLinkCap];          // link: node << 24 | I << 19 | behind fluid << 18 | owner code of the solid
-    float val[kQ - 1][kBlock];        // link value of population I at node n: val[I - 1][n]
+    uint32_t item[kLinkCap];          // link: node << 24 | I << 19 | behind fluid << 18 | owner code of the
+                                      // solid; then, on the in-list path, the link's value (FP32 bits)
+    float val[kQ][kBlock];            // population i streamed to node n: val[i][n] (FP32 storage: every
+                                      // pull; 16-bit storage: the link values only)
     int key[kRec];                    // owner code of the body in a force slot, -1 free
     unsigned long long sum[kCopies][kRec][6];  // fixed-point F, T of that body
     int wtot[kBlock / 64];
@@ -101,6 +103,46 @@ __device__ __forceinline__ void table_add(const FusedArgs &f, FusedLds &lds, int
         if (v[c]) atomicAdd(g + c, v[c]);
 }
 
+// Wait until this wavefront's vector memory loads are complete, loads into
+// LDS included (s_waitcnt vmcnt(0); the compiler does not track those).
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Workgroup barrier for LDS only: this wavefront's LDS operations complete,
+// then s_barrier; loads from global memory, those into LDS included, stay in
+// flight (a full barrier, or a fence on LDS, waits for them all).  The asm
+// clobbers memory, so the compiler moves no memory access across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Exclusive prefix of cnt (0 <= cnt < 64) over the workgroup, its total, and
+// whether any lane has flag set; through LDS (wtot: one word per wavefront)
+// with an LDS-only barrier.
+__device__ __forceinline__ int tile_scan(int cnt, bool flag, int *wtot, int &tot, bool &any)
+{
+    constexpr int kWaves = kBlock / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int pos = 0, wsum = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+        const unsigned long long mb = __ballot((cnt >> b) & 1);
+        pos += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u)) << b;
+        wsum += __popcll(mb) << b;
+    }
+    const bool wflag = __ballot(flag) != 0;  // on every lane (a ballot sees the active lanes only)
+    if (lane == 0) wtot[wv] = wsum | (wflag ? 1 << 20 : 0);  // wsum < 2^13
+    lds_barrier();
+    tot = 0;
+    int fl = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const int t = wtot[w];
+        if (w < wv) pos += t & 0xFFFFF;
+        tot += t & 0xFFFFF;
+        fl |= t;
+    }
+    any = (fl >> 20) & 1;
+    return pos;
+}
+
 // Index offsets of a node's periodic neighbours along each axis: m = to the
 // node at coordinate - 1, p = to the node at + 1.
 struct NbOff {
@@ -147,7 +189,8 @@ __device__ __forceinline__ uint32_t pull_src_rt(uint32_t idx, const NbOff &o, in
 // spin, q = 1/2 and no minimum image (their arm is about the reference
 // point).
 template <int S, int TX, int TY, int TZ>
-__device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds &lds, int x0, int y0, int z0, int j, int t)
+__device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds &lds, int x0, int y0, int z0, int j, int t,
+                                           bool inplace)
 {
     using St = Store<S>;
     using T = typename St::T;
@@ -173,7 +216,10 @@ __device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds &lds, in
     const double *B = sphere ? f.bodies + (size_t)(os - f.n_walls) * kBodyStride : f.wrec + (size_t)os * kBodyStride;
     const LinkGeo g = link_geo(sphere_k(B), exact_q, sphere, a.rho0, x, y, z, nx, ny, nz, I);
     const float vr = St::round(link_value(g.q, fk, fa, fb, behind, g.mw));
-    lds.val[I - 1][nl] = vr;
+    if (inplace)
+        lds.val[I][nl] = vr;
+    else
+        lds.item[j] = __float_as_uint(vr);  // the item is consumed: its slot takes the value
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double mom = link_momentum(fk, vr, I, a.rho0);
     link_force(mom, I, g, acc);
@@ -212,14 +258,34 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
     const NbOff no = nb_off(x, y, z, nx, ny, nz);
     auto src_idx = [&](int i) { return pull_src(idx, no, i); };
 
-    // 1. owner codes of the node and of its 18 pull sources
+    // 1. owner codes of the node and of its 18 pull sources (loaded before
+    //    anything else, so that waiting for them waits for nothing later)
     const uint16_t o = in ? *at(a.own, idx) : uint16_t(0);
-    const bool fluid = in && o >= kVacated;
     uint16_t on[kQ];
-    uint32_t solid = 0;  // pull sources owned by a solid
-    if (fluid) {
+    if (in) {
 #pragma unroll
         for (int i = 1; i < kQ; ++i) on[i] = *at(a.own, src_idx(i));
+    }
+    const bool fluid = in && o >= kVacated;
+    lds_barrier();  // the previous tile's readers of lds are done
+    if constexpr (S == 0) {
+        // FP32 storage: the node's 19 pulls go straight from HBM into
+        // lds.val, in flight while the tile's links are listed and formed.
+        // The owner codes are waited for first: the compiler does not count
+        // loads into LDS, so a later wait for an owner code would wait for
+        // all of them.
+        wait_vmem();
+        if (fluid) {
+            const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);  // the wavefront's LDS row offset
+#pragma unroll
+            for (int i = 0; i < kQ; ++i)
+                __builtin_amdgcn_global_load_lds(src + (size_t)i * Ns + (i ? src_idx(i) : idx),
+                                                 (__attribute__((address_space(3))) void *)&lds.val[i][wbase], 4, 0,
+                                                 0);
+        }
+    }
+    uint32_t solid = 0;  // pull sources owned by a solid
+    if (fluid) {
 #pragma unroll
         for (int i = 1; i < kQ; ++i)
             if (on[i] < kVacated) solid |= 1u << i;
@@ -231,16 +297,20 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
         for (int i = 1; i < kQ; ++i)
             if (CZ[i] == 1) m &= ~(1u << i);
     }
-    __syncthreads();  // the previous tile's readers of lds are done
     for (int k = tid; k < kRec; k += kBlock) lds.key[k] = -1;
     for (int k = tid; k < kCopies * kRec * 6; k += kBlock) (&lds.sum[0][0][0])[k] = 0ull;
     int tot;
-    const int pos = block_scan(__popc(m), lds.wtot, tot);  // its barrier also publishes the table's reset
-    if (tot == 0 && __syncthreads_or(fluid) == 0) return;
+    bool any_fluid;
+    const int pos = tile_scan(__popc(m), fluid, lds.wtot, tot, any_fluid);  // its barrier also publishes the table's reset
+    if (!any_fluid) return;
 
     // 2. the tile's links, listed and spread over the workgroup, in rounds
     //    of kLinkCap (the first from the codes in registers, later ones, rare,
-    //    load them again)
+    //    load them again).  A link's value goes into its list slot while the
+    //    pulls into lds.val may still be landing (one round); with several
+    //    rounds the pulls are waited for and the values go into lds.val.
+    const bool inplace = S != 0 || tot > kLinkCap;  // the same on every lane
+    if (S == 0 && inplace) wait_vmem();  // before the barrier below
     auto item = [&](int i, uint32_t code) {
         const uint32_t behind = ((solid >> opp(i)) & 1u) ^ 1u;
         return ((uint32_t)tid << 24) | ((uint32_t)i << 19) | (behind << 18) | code;
@@ -256,7 +326,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
     }
     for (int base = 0; base < tot; base += kLinkCap) {
         if (base) {
-            __syncthreads();  // the previous round's list is processed
+            lds_barrier();  // the previous round's list is processed
             int k = pos;
 #pragma unroll 1
             for (int i = 1; i < kQ; ++i)
@@ -266,9 +336,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
                     ++k;
                 }
         }
-        __syncthreads();
+        lds_barrier();  // the list is written (an LDS-only barrier: the pulls stay in flight)
         const int n = min(kLinkCap, tot - base);
-        for (int j = tid; j < n; j += kBlock) fused_link<S, TX, TY, TZ>(f, lds, x0, y0, z0, j, t);
+        for (int j = tid; j < n; j += kBlock) fused_link<S, TX, TY, TZ>(f, lds, x0, y0, z0, j, t, inplace);
     }
     if (tot > 0) {
         __syncthreads();  // the link values and the tile's body sums are complete
@@ -291,15 +361,26 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
     // 3. pull, collide and store (whole wavefronts; none with no fluid lane)
     if (!in || __ballot(fluid) == 0) return;
     float g[kQ];
+    if (S == 0) wait_vmem();  // this wavefront's pulls have landed in lds.val
     if (!fluid) {
 #pragma unroll
         for (int i = 0; i < kQ; ++i) g[i] = 0.0f;
+    } else if (S == 0) {
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) g[i] = lds.val[i][tid];
+        if (!inplace) {
+            // the node's link values from its list slots: pos, then in
+            // direction order
+#pragma unroll
+            for (int i = 1; i < kQ; ++i)
+                if ((m >> i) & 1u) g[i] = __uint_as_float(lds.item[pos + __popc(m & ((1u << i) - 1u))]);
+        }
     } else {
 #pragma unroll
         for (int i = 0; i < kQ; ++i) g[i] = St::ld(at(src + (size_t)i * Ns, i ? src_idx(i) : idx));
 #pragma unroll
         for (int i = 1; i < kQ; ++i)
-            if ((m >> i) & 1u) g[i] = lds.val[i - 1][tid];
+            if ((m >> i) & 1u) g[i] = lds.val[i][tid];
     }
     if (fluid && z == a.zieb_z) zieb_plane<S>(a, src, idx, g);
     collide_store<S>(a, g, fluid, idx, dst);
