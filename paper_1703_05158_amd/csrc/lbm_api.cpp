@@ -1455,6 +1455,7 @@ struct lbm_batch_ctx {
     bool own_stream = false;
     BatchMember *d_members = nullptr;
     int *d_cur = nullptr;
+    int *d_queue = nullptr;        // kQueueInts: tile queues, zero between steps
     int *h_cur = nullptr;          // pinned
     BatchStepArgs bs{};
     int shape = kTile64x2x2;       // tile shape of the batched step kernel
@@ -1494,7 +1495,7 @@ lbm_status batch_enqueue(lbm_batch_ctx *b)
 {
     BHIP_TRY(b, launch_batch_step(b->storage, b->shape, b->bs, b->grid_step, b->stream));
     BHIP_TRY(b, launch_batch_finish(b->bs, b->stream));
-    BHIP_TRY(b, launch_batch_flip(b->d_cur, (int)b->m.size(), b->stream));
+    BHIP_TRY(b, launch_batch_flip(b->d_cur, (int)b->m.size(), b->d_queue, b->stream));
     return LBM_OK;
 }
 
@@ -1566,11 +1567,15 @@ lbm_status batch_build(lbm_batch_ctx *b)
     }
     BHIP_TRY(b, hipMalloc((void **)&b->d_members, sizeof(BatchMember) * (size_t)n));
     if (!b->d_cur) BHIP_TRY(b, hipMalloc((void **)&b->d_cur, sizeof(int) * (size_t)n));
+    if (!b->d_queue) {
+        BHIP_TRY(b, hipMalloc((void **)&b->d_queue, sizeof(int) * kQueueInts));
+        BHIP_TRY(b, hipMemsetAsync(b->d_queue, 0, sizeof(int) * kQueueInts, b->stream));
+    }
     if (!b->h_cur) BHIP_TRY(b, hipHostMalloc((void **)&b->h_cur, sizeof(int) * (size_t)n));
     BHIP_TRY(b, hipMemcpyAsync(b->d_members, hm.data(), sizeof(BatchMember) * (size_t)n, hipMemcpyHostToDevice,
                                b->stream));
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
-    b->bs = BatchStepArgs{b->d_members, b->d_cur, n, tiles, forces};
+    b->bs = BatchStepArgs{b->d_members, b->d_cur, b->d_queue, n, tiles, forces};
     int dev = 0, cus = 0;
     BHIP_TRY(b, hipGetDevice(&dev));
     BHIP_TRY(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1592,6 +1597,7 @@ void lbm_batch_destroy(lbm_batch b)
     if (!b) return;
     batch_release(b);
     if (b->d_cur) (void)hipFree(b->d_cur);
+    if (b->d_queue) (void)hipFree(b->d_queue);
     if (b->h_cur) (void)hipHostFree(b->h_cur);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
@@ -1714,10 +1720,14 @@ lbm_status lbm_batch_autotune(lbm_batch b, int32_t trial_steps, int32_t *shape_o
     for (int k = 0; k < kNumTileShapes; ++k) {
         b->shape = k;
         if ((st = batch_build(b)) != LBM_OK) return st;
+        // each launch followed by the reset of the tile queues (a flip of no member)
         BHIP_TRY(b, launch_batch_step(b->storage, k, b->bs, b->grid_step, b->stream));
+        BHIP_TRY(b, launch_batch_flip(b->d_cur, 0, b->d_queue, b->stream));
         BHIP_TRY(b, hipEventRecord(ev.e0, b->stream));
-        for (int i = 0; i < trial_steps; ++i)
+        for (int i = 0; i < trial_steps; ++i) {
             BHIP_TRY(b, launch_batch_step(b->storage, k, b->bs, b->grid_step, b->stream));
+            BHIP_TRY(b, launch_batch_flip(b->d_cur, 0, b->d_queue, b->stream));
+        }
         BHIP_TRY(b, hipEventRecord(ev.e1, b->stream));
         BHIP_TRY(b, hipEventSynchronize(ev.e1));
         float ms = 0.f;

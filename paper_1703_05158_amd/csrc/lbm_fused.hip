@@ -441,16 +441,25 @@ __global__ __launch_bounds__(kBlock) void k_zero_fix(unsigned long long *p, int 
 // of the global tile range, so that each XCD works on neighbouring tiles of
 // the same members.
 template <int S, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_batch_fused(BatchStepArgs b)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_batch_fused(BatchStepArgs b)
 {
     __shared__ FusedLds lds;
-    const int xcd = blockIdx.x & 7, stride = gridDim.x >> 3;
+    __shared__ int next[2];  // the workgroup's tile of this iteration and of the next, in turn
+    const int xcd = blockIdx.x & 7;
     const int lo = (int)((long long)b.total_tiles * xcd / 8), hi = (int)((long long)b.total_tiles * (xcd + 1) / 8);
+    int *q = b.queue + xcd * kQueueStride;
+    if (threadIdx.x == 0) next[0] = atomicAdd(q, 1);
+    lds_barrier();
     // the member of the previous tile is kept: a workgroup's next tile is
     // usually in the same member
     int mb = 0, me = 0;
     FusedArgs f{};
-    for (int gt = lo + (int)(blockIdx.x >> 3); gt < hi; gt += stride) {
+    for (int k = 0;; ++k) {
+        const int gt = lo + __builtin_amdgcn_readfirstlane(next[k & 1]);
+        if (gt >= hi) break;
+        // the next tile is taken now, its atomic in flight during this one
+        int pre = 0;
+        if (threadIdx.x == 0) pre = atomicAdd(q, 1);
         if (gt < mb || gt >= me) {
             int m = 0, top = b.n;  // largest m with tile_begin[m] <= gt
             while (top - m > 1) {
@@ -468,6 +477,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused(BatchStepArgs b)
             f = uniform(t);
         }
         fused_tile<S, TX, TY, TZ>(f, gt - mb, lds);
+        if (threadIdx.x == 0) next[(k + 1) & 1] = pre;
+        lds_barrier();
     }
 }
 
@@ -485,10 +496,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_finish(BatchStepArgs b)
     finish_value(b.members[m].fin, g - b.members[m].force_begin);
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch_flip(int *cur, int n)
+__global__ __launch_bounds__(kBlock) void k_batch_flip(int *cur, int n, int *queue)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) cur[i] ^= 1;
+    if (i < kQueueInts) queue[i] = 0;  // the tile queues of the next step
 }
 
 template <int S>
@@ -604,9 +616,9 @@ hipError_t launch_batch_finish(const BatchStepArgs &b, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_batch_flip(int *cur, int n, hipStream_t s)
+hipError_t launch_batch_flip(int *cur, int n, int *queue, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_flip, dim3(nblk(n)), dim3(kBlock), 0, s, cur, n);
+    hipLaunchKernelGGL(k_batch_flip, dim3(nblk(std::max(n, kQueueInts))), dim3(kBlock), 0, s, cur, n, queue);
     return hipGetLastError();
 }
 

@@ -137,9 +137,15 @@ struct BatchMember {
     int force_begin;              // global index of the member's first force entry (6 per body and wall)
 };
 
+// Tile queues of the batched step: one counter per XCD, kQueueStride ints
+// apart (separate cache lines), zero before each step.
+constexpr int kQueueStride = 32;
+constexpr int kQueueInts = 8 * kQueueStride;
+
 struct BatchStepArgs {
     const BatchMember *members;
     const int *cur;               // [n]: member m's state is in pop[cur[m]]
+    int *queue;                   // [kQueueInts]: the XCDs' next tile counters
     int n;
     int total_tiles;
     int total_forces;
@@ -192,7 +198,7 @@ hipError_t static_fix_scratch(unsigned long long **out);
 hipError_t launch_batch_step(int storage, int shape, const BatchStepArgs &b, int grid, hipStream_t s);
 int batch_step_blocks_per_cu(int storage, int shape);   // resident workgroups per CU of the persistent step kernel
 hipError_t launch_batch_finish(const BatchStepArgs &b, hipStream_t s);
-hipError_t launch_batch_flip(int *cur, int n, hipStream_t s);
+hipError_t launch_batch_flip(int *cur, int n, int *queue, hipStream_t s);
 
 hipError_t launch_zieb_update(int storage, const ZiebArgs &z, hipStream_t s);
 hipError_t launch_adj_collide(const AdjStepArgs &g, hipStream_t s);
