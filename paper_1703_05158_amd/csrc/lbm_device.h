@@ -45,6 +45,10 @@ template <> struct Store<0> {
     static __device__ __forceinline__ void st(T *p, float v) { *p = v; }
     static __device__ __forceinline__ void stnt(T *p, float v) { __builtin_nontemporal_store(v, p); }
     static __device__ __forceinline__ float round(float v) { return v; }
+    // a stored value as the 32-bit word a load into LDS leaves (16-bit
+    // values zero-extended), and back
+    static __device__ __forceinline__ float from_bits(uint32_t w) { return __uint_as_float(w); }
+    static __device__ __forceinline__ uint32_t to_bits(float v) { return __float_as_uint(v); }
 };
 template <> struct Store<1> {
     using T = _Float16;
@@ -52,6 +56,11 @@ template <> struct Store<1> {
     static __device__ __forceinline__ void st(T *p, float v) { *p = (_Float16)v; }
     static __device__ __forceinline__ void stnt(T *p, float v) { __builtin_nontemporal_store((_Float16)v, p); }
     static __device__ __forceinline__ float round(float v) { return (float)(_Float16)v; }
+    static __device__ __forceinline__ float from_bits(uint32_t w)
+    {
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)w);
+    }
+    static __device__ __forceinline__ uint32_t to_bits(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
 };
 template <> struct Store<2> {  // bfloat16 as raw bits, round to nearest even
     using T = uint16_t;
@@ -65,6 +74,8 @@ template <> struct Store<2> {  // bfloat16 as raw bits, round to nearest even
     static __device__ __forceinline__ void st(T *p, float v) { *p = bits(v); }
     static __device__ __forceinline__ void stnt(T *p, float v) { __builtin_nontemporal_store(bits(v), p); }
     static __device__ __forceinline__ float round(float v) { return __uint_as_float((uint32_t)bits(v) << 16); }
+    static __device__ __forceinline__ float from_bits(uint32_t w) { return __uint_as_float(w << 16); }
+    static __device__ __forceinline__ uint32_t to_bits(float v) { return bits(v); }
 };
 
 // Element `e` of an array whose byte size fits in 32 bits: the offset is a

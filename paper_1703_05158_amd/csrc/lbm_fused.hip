@@ -48,8 +48,8 @@ constexpr int kCopies = 4;      // copies of the table's sums (by lane), so fewe
 struct FusedLds {
     uint32_t item[kLinkCap];          // link: node << 24 | I << 19 | behind fluid << 18 | owner code of the
                                       // solid; then, on the in-list path, the link's value (FP32 bits)
-    float val[kQ][kBlock];            // population i streamed to node n: val[i][n] (FP32 storage: every
-                                      // pull; 16-bit storage: the link values only)
+    uint32_t val[kQ][kBlock];         // population i streamed to node n: val[i][n], as the stored value's
+                                      // bits (16-bit storage: zero-extended)
     int key[kRec];                    // owner code of the body in a force slot, -1 free
     unsigned long long sum[kCopies][kRec][6];  // fixed-point F, T of that body
     int wtot[kBlock / 64];
@@ -217,7 +217,7 @@ __device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds &lds, in
     const LinkGeo g = link_geo(sphere_k(B), exact_q, sphere, a.rho0, x, y, z, nx, ny, nz, I);
     const float vr = St::round(link_value(g.q, fk, fa, fb, behind, g.mw));
     if (inplace)
-        lds.val[I][nl] = vr;
+        lds.val[I][nl] = St::to_bits(vr);
     else
         lds.item[j] = __float_as_uint(vr);  // the item is consumed: its slot takes the value
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -268,20 +268,21 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
     }
     const bool fluid = in && o >= kVacated;
     lds_barrier();  // the previous tile's readers of lds are done
-    if constexpr (S == 0) {
-        // FP32 storage: the node's 19 pulls go straight from HBM into
-        // lds.val, in flight while the tile's links are listed and formed.
-        // The owner codes are waited for first: the compiler does not count
-        // loads into LDS, so a later wait for an owner code would wait for
-        // all of them.
+    {
+        // the node's 19 pulls go straight from HBM into lds.val (one word
+        // per lane, 16-bit values zero-extended), in flight while the tile's
+        // links are listed and formed.  The owner codes are waited for
+        // first: the compiler does not count loads into LDS, so a later wait
+        // for an owner code would wait for all of them.
         wait_vmem();
+        constexpr int kBytes = S == 0 ? 4 : 2;  // an int: the builtin takes a 32-bit size
         if (fluid) {
             const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);  // the wavefront's LDS row offset
 #pragma unroll
             for (int i = 0; i < kQ; ++i)
                 __builtin_amdgcn_global_load_lds(src + (size_t)i * Ns + (i ? src_idx(i) : idx),
-                                                 (__attribute__((address_space(3))) void *)&lds.val[i][wbase], 4, 0,
-                                                 0);
+                                                 (__attribute__((address_space(3))) void *)&lds.val[i][wbase],
+                                                 kBytes, 0, 0);
         }
     }
     uint32_t solid = 0;  // pull sources owned by a solid
@@ -309,8 +310,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
     //    load them again).  A link's value goes into its list slot while the
     //    pulls into lds.val may still be landing (one round); with several
     //    rounds the pulls are waited for and the values go into lds.val.
-    const bool inplace = S != 0 || tot > kLinkCap;  // the same on every lane
-    if (S == 0 && inplace) wait_vmem();  // before the barrier below
+    const bool inplace = tot > kLinkCap;  // the same on every lane
+    if (inplace) wait_vmem();  // before the barrier below
     auto item = [&](int i, uint32_t code) {
         const uint32_t behind = ((solid >> opp(i)) & 1u) ^ 1u;
         return ((uint32_t)tid << 24) | ((uint32_t)i << 19) | (behind << 18) | code;
@@ -361,13 +362,13 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
     // 3. pull, collide and store (whole wavefronts; none with no fluid lane)
     if (!in || __ballot(fluid) == 0) return;
     float g[kQ];
-    if (S == 0) wait_vmem();  // this wavefront's pulls have landed in lds.val
+    wait_vmem();  // this wavefront's pulls have landed in lds.val
     if (!fluid) {
 #pragma unroll
         for (int i = 0; i < kQ; ++i) g[i] = 0.0f;
-    } else if (S == 0) {
+    } else {
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) g[i] = lds.val[i][tid];
+        for (int i = 0; i < kQ; ++i) g[i] = St::from_bits(lds.val[i][tid]);
         if (!inplace) {
             // the node's link values from its list slots: pos, then in
             // direction order
@@ -375,12 +376,6 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
             for (int i = 1; i < kQ; ++i)
                 if ((m >> i) & 1u) g[i] = __uint_as_float(lds.item[pos + __popc(m & ((1u << i) - 1u))]);
         }
-    } else {
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) g[i] = St::ld(at(src + (size_t)i * Ns, i ? src_idx(i) : idx));
-#pragma unroll
-        for (int i = 1; i < kQ; ++i)
-            if ((m >> i) & 1u) g[i] = lds.val[i][tid];
     }
     if (fluid && z == a.zieb_z) zieb_plane<S>(a, src, idx, g);
     collide_store<S>(a, g, fluid, idx, dst);
