@@ -97,13 +97,20 @@ __device__ __forceinline__ int wrap_add(int a, int d, int n)
     return r < 0 ? r + n : (r >= n ? r - n : r);
 }
 
-// Workgroups go round-robin over the 8 XCDs: give each XCD a contiguous
-// range of the nblocks work items, so that neighbouring items share an L2.
+// Workgroups go round-robin over the 8 XCDs.  The work items are handed out
+// in chunks of kXcdChunk consecutive items, chunk c to XCD c mod 8, so that
+// neighbouring items share an L2 while every XCD draws from the whole range
+// (a contiguous eighth per XCD loads the XCDs unevenly wherever the work is
+// not spread evenly over the range).  Item i of XCD x's share, in order:
+constexpr int kXcdChunk = 128;
+
+__device__ __forceinline__ int xcd_item(int x, int i) { return ((i / kXcdChunk) * 8 + x) * kXcdChunk + i % kXcdChunk; }
+
 __device__ __forceinline__ int xcd_remap(int b, int nblocks)
 {
-    const int per = nblocks >> 3;
-    if (b >= (per << 3)) return b;
-    return (b & 7) * per + (b >> 3);
+    const int full = nblocks / (8 * kXcdChunk) * (8 * kXcdChunk);
+    if (b >= full) return b;  // the last partial round in plain order
+    return xcd_item(b & 7, b >> 3);
 }
 
 // A copy of v that the compiler knows to be the same in every lane (the

@@ -432,17 +432,17 @@ __global__ __launch_bounds__(kBlock) void k_zero_fix(unsigned long long *p, int 
 
 // Persistent fused step over the tiles of many lattices, all with the
 // batch's tile shape.  Member m owns the global tiles [tile_begin[m],
-// tile_begin[m + 1]); XCD k (workgroups k, k + 8, ...) walks the k-th eighth
-// of the global tile range, so that each XCD works on neighbouring tiles of
-// the same members.
+// tile_begin[m + 1]); XCD k (workgroups k, k + 8, ...) takes its share of
+// the global tile range (runs of neighbouring tiles, by xcd_item) from its
+// own queue, so that each XCD works on neighbouring tiles of the same
+// members while every XCD draws from all of them.
 template <int S, int TX, int TY, int TZ>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_batch_fused(BatchStepArgs b)
 {
     __shared__ FusedLds lds;
     __shared__ int next[2];  // the workgroup's tile of this iteration and of the next, in turn
     const int xcd = blockIdx.x & 7;
-    const int lo = (int)((long long)b.total_tiles * xcd / 8), hi = (int)((long long)b.total_tiles * (xcd + 1) / 8);
-    int *q = b.queue + xcd * kQueueStride;
+    int *q = b.queue + xcd * kQueueStride;  // the XCD's tiles in turn, by xcd_item
     if (threadIdx.x == 0) next[0] = atomicAdd(q, 1);
     lds_barrier();
     // the member of the previous tile is kept: a workgroup's next tile is
@@ -450,8 +450,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) 
     int mb = 0, me = 0;
     FusedArgs f{};
     for (int k = 0;; ++k) {
-        const int gt = lo + __builtin_amdgcn_readfirstlane(next[k & 1]);
-        if (gt >= hi) break;
+        const int gt = xcd_item(xcd, __builtin_amdgcn_readfirstlane(next[k & 1]));
+        if (gt >= b.total_tiles) break;  // the XCD's later items lie beyond too
         // the next tile is taken now, its atomic in flight during this one
         int pre = 0;
         if (threadIdx.x == 0) pre = atomicAdd(q, 1);

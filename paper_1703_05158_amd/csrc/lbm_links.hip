@@ -426,10 +426,10 @@ __global__ __launch_bounds__(kBlock) void k_links(LinkArgs a)
     __shared__ double s_red[kWaves][6];
     const int b = blockIdx.x;
     if (b < a.nb) {
-        // workgroups go round-robin over the 8 XCDs: each XCD takes a
-        // contiguous range of the spheres in processing order (Morton order
-        // of the centres when the host set them), so that neighbouring
-        // spheres, which share population lines, share an L2
+        // workgroups go round-robin over the 8 XCDs: each XCD takes runs
+        // of consecutive spheres in processing order (Morton order of the
+        // centres when the host set them), so that neighbouring spheres,
+        // which share population lines, share an L2
         const int sb = xcd_remap(b, a.nb);
         sphere_block<S>(a, a.order ? a.order[sb] : sb, L, s_red);
     }
