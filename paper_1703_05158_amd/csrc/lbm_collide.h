@@ -102,11 +102,12 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g
         const float Qn = pxx * pxx + pyy * pyy + pzz * pzz + 2.0f * (pxy * pxy + pxz * pxz + pyz * pyz);
         tau = 0.5f * (a.tau0 + __builtin_sqrtf(a.tau0 * a.tau0 + a.smag_k * __builtin_sqrtf(Qn) * ir));
     } else {
-        // 16-bit storage: the strain-rate norm and tau* in FP64
+        // 16-bit storage: the strain-rate norm accumulated, and its square
+        // root taken, in FP64; tau* from it in FP32 like the rest
         const double Qn = (double)pxx * pxx + (double)pyy * pyy + (double)pzz * pzz +
                           2.0 * ((double)pxy * pxy + (double)pxz * pxz + (double)pyz * pyz);
-        const double t0 = (double)a.tau0;
-        tau = (float)(0.5 * (t0 + sqrt(t0 * t0 + (double)a.smag_k * sqrt(Qn) / (double)rho)));
+        const float sq = (float)sqrt(Qn);
+        tau = 0.5f * (a.tau0 + __builtin_sqrtf(a.tau0 * a.tau0 + a.smag_k * sq * ir));
     }
     const float om = __builtin_amdgcn_rcpf(tau);
     const float om1 = 1.0f - om;

@@ -57,15 +57,19 @@ struct FusedLds {
 
 // v 2^32 rounded to the nearest integer, ties to even, as a two's-complement
 // 64-bit value.  While |v 2^32| < 2^51 one FP64 add of 1.5 2^52 leaves that
-// integer in the low mantissa bits; larger values take the library
-// conversion, which rounds the same way.
-__device__ __forceinline__ unsigned long long to_fix(double v)
+// integer in the low mantissa bits (to_fix_fast, for |v| < kFixFastLimit);
+// larger values take the library conversion, which rounds the same way.
+constexpr double kFixFastLimit = 524288.0;  // 2^19
+
+__device__ __forceinline__ unsigned long long to_fix_fast(double v)
 {
     constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
-    if (__builtin_fabs(v) < 524288.0) {
-        const double t = __builtin_fma(v, kFixScale, kMagic);
-        return (unsigned long long)(__double_as_longlong(t) - __double_as_longlong(kMagic));
-    }
+    const double t = __builtin_fma(v, kFixScale, kMagic);
+    return (unsigned long long)(__double_as_longlong(t) - __double_as_longlong(kMagic));
+}
+
+__device__ __forceinline__ unsigned long long to_fix_slow(double v)
+{
     return (unsigned long long)__double2ll_rn(v * kFixScale);
 }
 
@@ -91,8 +95,7 @@ __device__ __forceinline__ void table_add(const FusedArgs &f, FusedLds &lds, int
         if (cur == -1 || cur == key) {
             unsigned long long *d = lds.sum[threadIdx.x & (kCopies - 1)][s];
 #pragma unroll
-            for (int c = 0; c < 6; ++c)
-                if (v[c]) atomicAdd(d + c, v[c]);
+            for (int c = 0; c < 6; ++c) atomicAdd(d + c, v[c]);  // zeros too: no test per component
             return;
         }
         s = (s + 1) & (kRec - 1);
@@ -225,13 +228,23 @@ __device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds &lds, in
     link_force(mom, I, g, acc);
     unsigned long long v[6];
     // F = -mom c_I: its fixed-point components are -c M with M = fix(mom)
-    // (the rounding is odd-symmetric)
-    const unsigned long long M = to_fix(mom);
+    // (the rounding is odd-symmetric).  One range test for the four
+    // conversions (to_fix's two ways, taken together).
     const int cI[3] = {dcx(I), dcy(I), dcz(I)};
+    unsigned long long M;
+    const double big =
+        fmax(fmax(__builtin_fabs(mom), __builtin_fabs(acc[3])), fmax(__builtin_fabs(acc[4]), __builtin_fabs(acc[5])));
+    if (big < kFixFastLimit) {
+        M = to_fix_fast(mom);
+#pragma unroll
+        for (int c = 3; c < 6; ++c) v[c] = to_fix_fast(acc[c]);
+    } else {
+        M = to_fix_slow(mom);
+#pragma unroll
+        for (int c = 3; c < 6; ++c) v[c] = to_fix_slow(acc[c]);
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) v[c] = cI[c] > 0 ? 0ull - M : (cI[c] < 0 ? M : 0ull);
-#pragma unroll
-    for (int c = 3; c < 6; ++c) v[c] = to_fix(acc[c]);
     table_add(f, lds, os, v, t);
 }
 
