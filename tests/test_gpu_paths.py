@@ -156,3 +156,36 @@ def test_profile_parts(torch_stream):
         assert parts["whole"] == pytest.approx(total, rel=1e-3, abs=1e-3)
         lat.profile(False)
         lat.close()
+
+
+def test_forces_read_or_not_give_the_same_state(torch_stream):
+    """The step's force sums are finished lazily (by the next fused step, or
+    when read).  A handle that reads its forces after every step and one that
+    reads them only at the end, through fused steps, a switch to the split
+    path and back, a no-alloc step and a checkpoint, end bit for bit alike."""
+    import torch
+    from paper_1703_05158_amd import Lattice
+    case = W.case_box(n=(40, 36, 44), n_spheres=6, radius=(2.0, 4.5), v_sigma=0.01, w_sigma=0.005, seed=12,
+                      drift=True)
+    lats = [Lattice.from_case(case, stream=torch_stream) for _ in range(2)]
+    info = lats[0].info()
+    hist = torch.zeros((6 * (info["n_bodies"] + info["n_walls"]),), dtype=torch.float64, device="cuda")
+    plan = ["fused", "fused", "split", "fused", "noalloc", "fused", "state", "fused"]
+    for n, what in enumerate(plan, start=1):
+        for k, lat in enumerate(lats):
+            if what == "state":
+                lat.set_state(lat.get_state())  # a checkpoint round trip mid-run
+                continue
+            lat.set_bodies(*case.bodies_at(n))
+            lat.set_step_path("split" if what == "split" else "fused")
+            (lat.step_noalloc if what == "noalloc" else lat.step)(1)
+            if k == 0:
+                lat.get_forces_device(hist)
+    np.testing.assert_array_equal(lats[0].get_populations(), lats[1].get_populations())
+    F0, T0 = lats[0].get_forces()
+    F1, T1 = lats[1].get_forces()
+    np.testing.assert_array_equal(F0, F1)
+    np.testing.assert_array_equal(T0, T1)
+    np.testing.assert_array_equal(hist.cpu().numpy().reshape(-1, 6)[:, :3], F0)
+    for lat in lats:
+        lat.close()
