@@ -268,8 +268,9 @@ lbm_status lbm_profile_read(lbm_handle h, double *ms_total, int64_t *launches);
 lbm_status lbm_profile_read_parts(lbm_handle h, double *ms, int64_t *steps);
 
 /* Kernels that make a step (see lbm_step).  FUSED: one kernel per step does
- * links, streaming and collision, then a small kernel turns the fixed-point
- * force sums into FP64.  SPLIT: the boundary-link pass, then the
+ * links, streaming and collision; its fixed-point force sums become FP64
+ * forces when they are read or at the start of the next fused step.  SPLIT:
+ * the boundary-link pass, then the
  * pull-collide kernel.  Both give the same populations bit for bit; their
  * forces agree to rounding.  The drag gradient's reverse sweep uses the
  * split path's kernels whatever the setting.  Errors: ARG. */
@@ -357,8 +358,8 @@ lbm_status lbm_autotune_tile(lbm_handle h, int32_t trial_steps, const char *cach
  *             changed since the batch was built with STATE).
  *   stream  : hipStream_t for the batch's work, or NULL for a stream of its
  *             own (default priority).
- * lbm_batch_step waits for the members' queued work, replays the graph
- * nsteps times, synchronises, and advances every member's state and step
+ * lbm_batch_step waits for the members' queued work, replays the graphs
+ * for nsteps steps, synchronises, and advances every member's state and step
  * counter; forces of the last step are then read per member as usual.  The
  * NaN guard does not run in batched steps.  Errors: ARG, STATE (a member not
  * initialised, or with bodies pending), HIP, OOM (text in
