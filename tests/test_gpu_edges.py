@@ -254,3 +254,28 @@ def test_sphere_at_the_radius_limit(torch_stream):
         advance(o, lat, case, 0, 12)
         _check(o, lat)
         lat.close()
+
+
+def test_long_axis_geometry(torch_stream):
+    """Spheres straddling and drifting across the periodic ends of an
+    8192-node axis, and one far from the origin: the re-rasterisation takes offsets from each
+    sphere's box origin, so its FP32 bounds hold at any coordinate size.
+    Owner maps bit for bit, populations and forces at the FP32 bars."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    nx, ny, nz = 20, 18, 8192
+    X = np.array([[9.3, 8.7, 8190.6], [10.1, 9.4, 1.2], [6.2, 5.5, 4096.35], [13.7, 11.1, 8185.45],
+                  [9.0, 9.0, 8191.5]])
+    R = np.array([4.3, 3.7, 5.1, 2.9, 3.0])
+    V = np.array([[0.02, -0.01, 0.1], [-0.01, 0.02, -0.1], [0.01, 0.01, 0.05], [0.0, -0.02, 0.1],
+                  [0.01, 0.0, -0.1]])
+    case = W.Case(name="long_axis", nx=nx, ny=ny, nz=nz, tau0=0.7, smag_c=0.1, body_force=(0.0, 0.0, 1e-6),
+                  X=X, V=V, Omega=rng.normal(0.0, 0.005, (len(R), 3)), R=R,
+                  u_init=rng.normal(0.0, 0.005, (3, nz, ny, nx)), drift=True)
+    o, lat = make_pair(case, stream=torch_stream)
+    advance(o, lat, case, 0, 12)
+    np.testing.assert_array_equal(lat.get_owner(), o.owner())
+    pe = pop_rel_err(o, lat)
+    fe, te = force_rel_err(o, lat)
+    print(f"pop {pe:.2e}  F {fe:.2e}  T {te:.2e}")
+    assert pe <= 1e-5 and fe <= 1e-4 and te <= 1e-4
+    lat.close()
