@@ -82,7 +82,7 @@ def test_torch_function_and_directional_difference(torch_stream):
     J = fn(F, V)
     gF, gV = torch.autograd.grad(J, (F, V))
     J2, gF2, gV2 = Lattice.from_case(case, stream=torch_stream).drag_gradient(20, 5)
-    assert float(J) == pytest.approx(J2, rel=1e-12)
+    assert float(J.detach()) == pytest.approx(J2, rel=1e-12)
     assert np.allclose(gF.numpy(), gF2, rtol=1e-5) and np.allclose(gV.numpy(), gV2, rtol=1e-5, atol=1e-9)
     # J is linear in V: a directional difference on the GPU matches dJ/dV . d
     rng = np.random.Generator(np.random.PCG64(4))
