@@ -2,9 +2,10 @@
 // and store of a 256-node tile in one pass over HBM.
 //
 // Per tile (one workgroup, one node per thread):
-//  1. The owner codes of the tile and of a one-node periodic halo go into
-//     LDS; each thread issues the 19 pulls of its node (the streaming
-//     equation of Sec. 2.2).
+//  1. Each thread loads the owner codes of its node and of its 18 pull
+//     sources, and issues the pulls of its node whose source is fluid (the
+//     streaming equation of Sec. 2.2) straight into the tile's LDS array of
+//     populations.
 //  2. Each fluid node marks the directions whose pull source is a solid node
 //     (a cut link, Sec. 2.3); the links of the tile are listed in LDS and
 //     spread over the workgroup's threads.  Per link: the value of the
@@ -14,9 +15,10 @@
 //     behind it, which the tile's pulls have brought into the caches; and
 //     the momentum exchanged on the link (Sec. 2.3, force and torque), added
 //     as 64-bit fixed point to the tile's LDS table of bodies.
-//  3. Each node takes its link values in place of the pulled ones, then
-//     moments, the Smagorinsky relaxation time, BGK + Guo collision and the
-//     store follow as in the pull-collide kernel.
+//     The link's value goes into the LDS slot its pull would have filled.
+//  3. Each node takes its 19 values from LDS; moments, the Smagorinsky
+//     relaxation time, BGK + Guo collision and the store follow as in the
+//     pull-collide kernel.
 //  4. The tile's body sums go to the global fixed-point sums with one atomic
 //     add per body and component; a small kernel turns them into the FP64
 //     forces of the step.  Integer sums do not depend on the order of the
@@ -192,8 +194,7 @@ __device__ __forceinline__ uint32_t pull_src_rt(uint32_t idx, const NbOff &o, in
 // spin, q = 1/2 and no minimum image (their arm is about the reference
 // point).
 template <int S, int TX, int TY, int TZ>
-__device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds &lds, int x0, int y0, int z0, int j, int t,
-                                           bool inplace)
+__device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds &lds, int x0, int y0, int z0, int j, int t)
 {
     using St = Store<S>;
     using T = typename St::T;
@@ -219,10 +220,7 @@ __device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds &lds, in
     const double *B = sphere ? f.bodies + (size_t)(os - f.n_walls) * kBodyStride : f.wrec + (size_t)os * kBodyStride;
     const LinkGeo g = link_geo(sphere_k(B), exact_q, sphere, a.rho0, x, y, z, nx, ny, nz, I);
     const float vr = St::round(link_value(g.q, fk, fa, fb, behind, g.mw));
-    if (inplace)
-        lds.val[I][nl] = St::to_bits(vr);
-    else
-        lds.item[j] = __float_as_uint(vr);  // the item is consumed: its slot takes the value
+    lds.val[I][nl] = St::to_bits(vr);  // a slot no pull is loaded into
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double mom = link_momentum(fk, vr, I, a.rho0);
     link_force(mom, I, g, acc);
@@ -281,28 +279,27 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
     }
     const bool fluid = in && o >= kVacated;
     lds_barrier();  // the previous tile's readers of lds are done
-    {
-        // the node's 19 pulls go straight from HBM into lds.val (one word
-        // per lane, 16-bit values zero-extended), in flight while the tile's
-        // links are listed and formed.  The owner codes are waited for
-        // first: the compiler does not count loads into LDS, so a later wait
-        // for an owner code would wait for all of them.
-        wait_vmem();
-        constexpr int kBytes = S == 0 ? 4 : 2;  // an int: the builtin takes a 32-bit size
-        if (fluid) {
-            const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);  // the wavefront's LDS row offset
-#pragma unroll
-            for (int i = 0; i < kQ; ++i)
-                __builtin_amdgcn_global_load_lds(src + (size_t)i * Ns + (i ? src_idx(i) : idx),
-                                                 (__attribute__((address_space(3))) void *)&lds.val[i][wbase],
-                                                 kBytes, 0, 0);
-        }
-    }
+    // The owner codes are waited for before anything else is loaded: the
+    // compiler does not count loads into LDS, so a later wait for an owner
+    // code would wait for all of them.
+    wait_vmem();
     uint32_t solid = 0;  // pull sources owned by a solid
     if (fluid) {
 #pragma unroll
         for (int i = 1; i < kQ; ++i)
             if (on[i] < kVacated) solid |= 1u << i;
+        // the node's pulls from fluid sources go straight from HBM into
+        // lds.val (one word per lane, 16-bit values zero-extended), in
+        // flight while the tile's links are listed and formed; the slot of
+        // a cut link is left to the link's value
+        constexpr int kBytes = S == 0 ? 4 : 2;  // an int: the builtin takes a 32-bit size
+        const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);  // the wavefront's LDS row offset
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+            if (!((solid >> i) & 1u))
+                __builtin_amdgcn_global_load_lds(at(src + (size_t)i * Ns, i ? src_idx(i) : idx),
+                                                 (__attribute__((address_space(3))) void *)&lds.val[i][wbase],
+                                                 kBytes, 0, 0);
     }
     // cut links: not the inflow plane's directions from the removed domain
     uint32_t m = solid;
@@ -320,11 +317,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
 
     // 2. the tile's links, listed and spread over the workgroup, in rounds
     //    of kLinkCap (the first from the codes in registers, later ones, rare,
-    //    load them again).  A link's value goes into its list slot while the
-    //    pulls into lds.val may still be landing (one round); with several
-    //    rounds the pulls are waited for and the values go into lds.val.
-    const bool inplace = tot > kLinkCap;  // the same on every lane
-    if (inplace) wait_vmem();  // before the barrier below
+    //    load them again).  A link's value goes into its node's slot of
+    //    lds.val, which no pull is loaded into, so the pulls stay in flight.
     auto item = [&](int i, uint32_t code) {
         const uint32_t behind = ((solid >> opp(i)) & 1u) ^ 1u;
         return ((uint32_t)tid << 24) | ((uint32_t)i << 19) | (behind << 18) | code;
@@ -352,7 +346,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
         }
         lds_barrier();  // the list is written (an LDS-only barrier: the pulls stay in flight)
         const int n = min(kLinkCap, tot - base);
-        for (int j = tid; j < n; j += kBlock) fused_link<S, TX, TY, TZ>(f, lds, x0, y0, z0, j, t, inplace);
+        for (int j = tid; j < n; j += kBlock) fused_link<S, TX, TY, TZ>(f, lds, x0, y0, z0, j, t);
     }
     if (tot > 0) {
         __syncthreads();  // the link values and the tile's body sums are complete
@@ -375,20 +369,13 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
     // 3. pull, collide and store (whole wavefronts; none with no fluid lane)
     if (!in || __ballot(fluid) == 0) return;
     float g[kQ];
-    wait_vmem();  // this wavefront's pulls have landed in lds.val
+    wait_vmem();  // this wavefront's pulls have landed in lds.val (the link values are there since the barrier)
     if (!fluid) {
 #pragma unroll
         for (int i = 0; i < kQ; ++i) g[i] = 0.0f;
     } else {
 #pragma unroll
         for (int i = 0; i < kQ; ++i) g[i] = St::from_bits(lds.val[i][tid]);
-        if (!inplace) {
-            // the node's link values from its list slots: pos, then in
-            // direction order
-#pragma unroll
-            for (int i = 1; i < kQ; ++i)
-                if ((m >> i) & 1u) g[i] = __uint_as_float(lds.item[pos + __popc(m & ((1u << i) - 1u))]);
-        }
     }
     if (fluid && z == a.zieb_z) zieb_plane<S>(a, src, idx, g);
     collide_store<S>(a, g, fluid, idx, dst);
