@@ -49,6 +49,37 @@ __device__ __forceinline__ void zieb_plane(const StepArgs &a, const typename Sto
     }
 }
 
+// c . v for a lattice vector c (components -1, 0, 1, compile-time) over its
+// nonzero components only: a product with a zero component and a sum that
+// starts from zero are operations the compiler may not drop (signed zeros,
+// NaN), and here they would cost an instruction each.
+__device__ __forceinline__ float cdot(int c0, int c1, int c2, float v0, float v1, float v2)
+{
+    float s = 0.0f;
+    bool any = false;
+    if (c0) {
+        s = c0 > 0 ? v0 : -v0;
+        any = true;
+    }
+    if (c1) {
+        const float t = c1 > 0 ? v1 : -v1;
+        s = any ? s + t : t;
+        any = true;
+    }
+    if (c2) {
+        const float t = c2 > 0 ? v2 : -v2;
+        s = any ? s + t : t;
+    }
+    return s;
+}
+
+// s += t, where the first addition (first == true) takes t itself.
+__device__ __forceinline__ void acc_first(float &s, bool &first, float t)
+{
+    s = first ? t : s + t;
+    first = false;
+}
+
 // Collide the streamed deviations g of node idx and store the result into
 // dst.  Every lane of the wavefront stores: a store with lanes switched off
 // writes partial 128-byte lines, which cost a read-modify-write in HBM.  A
@@ -71,18 +102,19 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g
     }
     float rd = g[0], jx = 0.f, jy = 0.f, jz = 0.f;
     float sxx = 0.f, syy = 0.f, szz = 0.f, sxy = 0.f, sxz = 0.f, syz = 0.f;
+    bool fjx = true, fjy = true, fjz = true, fxx = true, fyy = true, fzz = true, fxy = true, fxz = true, fyz = true;
 #pragma unroll
     for (int i = 1; i <= 9; ++i) {
         rd += pe[i];
-        if (CX[i]) jx += CX[i] * po[i];
-        if (CY[i]) jy += CY[i] * po[i];
-        if (CZ[i]) jz += CZ[i] * po[i];
-        if (CX[i]) sxx += pe[i];
-        if (CY[i]) syy += pe[i];
-        if (CZ[i]) szz += pe[i];
-        if (CX[i] * CY[i]) sxy += CX[i] * CY[i] * pe[i];
-        if (CX[i] * CZ[i]) sxz += CX[i] * CZ[i] * pe[i];
-        if (CY[i] * CZ[i]) syz += CY[i] * CZ[i] * pe[i];
+        if (CX[i]) acc_first(jx, fjx, CX[i] > 0 ? po[i] : -po[i]);
+        if (CY[i]) acc_first(jy, fjy, CY[i] > 0 ? po[i] : -po[i]);
+        if (CZ[i]) acc_first(jz, fjz, CZ[i] > 0 ? po[i] : -po[i]);
+        if (CX[i]) acc_first(sxx, fxx, pe[i]);
+        if (CY[i]) acc_first(syy, fyy, pe[i]);
+        if (CZ[i]) acc_first(szz, fzz, pe[i]);
+        if (CX[i] * CY[i]) acc_first(sxy, fxy, CX[i] * CY[i] > 0 ? pe[i] : -pe[i]);
+        if (CX[i] * CZ[i]) acc_first(sxz, fxz, CX[i] * CZ[i] > 0 ? pe[i] : -pe[i]);
+        if (CY[i] * CZ[i]) acc_first(syz, fyz, CY[i] * CZ[i] > 0 ? pe[i] : -pe[i]);
     }
     const float rho = a.rho0 + rd;
     const float ir = __builtin_amdgcn_rcpf(rho);
@@ -102,11 +134,12 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g
         const float Qn = pxx * pxx + pyy * pyy + pzz * pzz + 2.0f * (pxy * pxy + pxz * pxz + pyz * pyz);
         tau = 0.5f * (a.tau0 + __builtin_sqrtf(a.tau0 * a.tau0 + a.smag_k * __builtin_sqrtf(Qn) * ir));
     } else {
-        // 16-bit storage: the strain-rate norm accumulated, and its square
-        // root taken, in FP64; tau* from it in FP32 like the rest
+        // 16-bit storage: the strain-rate norm accumulated in FP64; its
+        // square root (of a sum of squares: well conditioned) and tau* in
+        // FP32 like the rest
         const double Qn = (double)pxx * pxx + (double)pyy * pyy + (double)pzz * pzz +
                           2.0 * ((double)pxy * pxy + (double)pxz * pxz + (double)pyz * pyz);
-        const float sq = (float)sqrt(Qn);
+        const float sq = __builtin_sqrtf((float)Qn);
         tau = 0.5f * (a.tau0 + __builtin_sqrtf(a.tau0 * a.tau0 + a.smag_k * sq * ir));
     }
     const float om = __builtin_amdgcn_rcpf(tau);
@@ -134,8 +167,8 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g
 #pragma unroll
     for (int i = 1; i <= 9; ++i) {
         const bool axis = wgt(i) == wgt(1);
-        const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-        const float cF = CX[i] * a.fx + CY[i] * a.fy + CZ[i] * a.fz;
+        const float cu = cdot(CX[i], CY[i], CZ[i], ux, uy, uz);
+        const float cF = cdot(CX[i], CY[i], CZ[i], a.fx, a.fy, a.fz);
         const float ev = (axis ? a1 : a2) + cu * ((axis ? b1 : b2) * cu + (axis ? e1 : e2) * cF);
         const float od = (axis ? d1 : d2) * cu + (axis ? o1 : o2) * cF;
         const float vp = om1 * g[i] + (ev + od), vm = om1 * g[i + 9] + (ev - od);

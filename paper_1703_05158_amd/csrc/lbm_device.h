@@ -65,12 +65,9 @@ template <> struct Store<1> {
 template <> struct Store<2> {  // bfloat16 as raw bits, round to nearest even
     using T = uint16_t;
     static __device__ __forceinline__ float ld(const T *p) { return __uint_as_float((uint32_t)*p << 16); }
-    static __device__ __forceinline__ uint16_t bits(float v)
-    {
-        const uint32_t u = __float_as_uint(v);
-        if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-        return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-    }
+    // gfx950's conversion instruction (v_cvt_pk_bf16_f32) rounds to nearest
+    // even: one instruction where the rounding in integer arithmetic takes six
+    static __device__ __forceinline__ uint16_t bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
     static __device__ __forceinline__ void st(T *p, float v) { *p = bits(v); }
     static __device__ __forceinline__ void stnt(T *p, float v) { __builtin_nontemporal_store(bits(v), p); }
     static __device__ __forceinline__ float round(float v) { return __uint_as_float((uint32_t)bits(v) << 16); }
