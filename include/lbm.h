@@ -331,12 +331,13 @@ lbm_status lbm_get_tile(lbm_handle h, int32_t *shape);
 
 /* Tile-shape autotuner.  Times trial_steps launches of the step kernel for
  * every tile shape on the handle's current state (the launches write only
- * the spare population buffer, so the state does not advance) and keeps the
- * fastest.  cache_path (may be NULL) names a JSON object of integer shapes
+ * the spare population buffer, so the state does not advance), twice over
+ * the shapes, and keeps the shape with the fastest of its two times.  cache_path (may be NULL) names a JSON object of integer shapes
  * keyed "<gfx target>/<f32|f16|bf16>/<nx>x<ny>x<nz>": a key that is present
  * is used without timing; a new result is written back.  shape (may be
- * NULL) receives the chosen shape; us (may be NULL, 4 doubles) the average
- * kernel time per shape in microseconds, -1 where not timed.  Synchronises.
+ * NULL) receives the chosen shape; us (may be NULL, 4 doubles) the faster
+ * of each shape's two average kernel times in microseconds, -1 where not
+ * timed.  Synchronises.
  * Errors: STATE (before lbm_init_fields, or bodies set since the last step),
  * ARG (trial_steps < 1, cache not writable), HIP. */
 lbm_status lbm_autotune_tile(lbm_handle h, int32_t trial_steps, const char *cache_path, int32_t *shape,
@@ -374,9 +375,10 @@ void lbm_batch_destroy(lbm_batch b);
  * numbering as lbm_set_tile; 64x2x2 when every nx is a multiple of 64, else
  * 32x4x2 at creation).  lbm_batch_autotune times trial_steps launches of the
  * batched step kernel for every shape on the members' current states (the
- * launches write only the spare buffers, so no state advances), keeps the
- * fastest and returns it in shape (may be NULL), with the time per launch
- * in microseconds for each shape in us (may be NULL, 4 doubles).  Both
+ * launches write only the spare buffers, so no state advances), twice over
+ * the shapes, keeps the shape with the fastest of its two times and returns
+ * it in shape (may be NULL), with that time per launch in microseconds for
+ * each shape in us (may be NULL, 4 doubles).  Both
  * rebuild the captured graph.  Errors: ARG, STATE, HIP. */
 lbm_status lbm_batch_set_tile(lbm_batch b, int32_t shape);
 lbm_status lbm_batch_get_tile(lbm_batch b, int32_t *shape);

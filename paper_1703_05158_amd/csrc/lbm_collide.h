@@ -129,18 +129,20 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g
     const float pxy = sxy - rho * ux * uy;
     const float pxz = sxz - rho * ux * uz;
     const float pyz = syz - rho * uy * uz;
+    // tau*: square roots by the hardware instruction (within 1 ulp), not
+    // the correctly rounded sequence, which takes some fifteen instructions
     float tau;
     if (S == 0) {
         const float Qn = pxx * pxx + pyy * pyy + pzz * pzz + 2.0f * (pxy * pxy + pxz * pxz + pyz * pyz);
-        tau = 0.5f * (a.tau0 + __builtin_sqrtf(a.tau0 * a.tau0 + a.smag_k * __builtin_sqrtf(Qn) * ir));
+        tau = 0.5f * (a.tau0 + __builtin_amdgcn_sqrtf(a.tau0 * a.tau0 + a.smag_k * __builtin_amdgcn_sqrtf(Qn) * ir));
     } else {
         // 16-bit storage: the strain-rate norm accumulated in FP64; its
         // square root (of a sum of squares: well conditioned) and tau* in
         // FP32 like the rest
         const double Qn = (double)pxx * pxx + (double)pyy * pyy + (double)pzz * pzz +
                           2.0 * ((double)pxy * pxy + (double)pxz * pxz + (double)pyz * pyz);
-        const float sq = __builtin_sqrtf((float)Qn);
-        tau = 0.5f * (a.tau0 + __builtin_sqrtf(a.tau0 * a.tau0 + a.smag_k * sq * ir));
+        const float sq = __builtin_amdgcn_sqrtf((float)Qn);
+        tau = 0.5f * (a.tau0 + __builtin_amdgcn_sqrtf(a.tau0 * a.tau0 + a.smag_k * sq * ir));
     }
     const float om = __builtin_amdgcn_rcpf(tau);
     const float om1 = 1.0f - om;

@@ -43,19 +43,25 @@ namespace {
 
 using namespace dev;
 
-constexpr int kLinkCap = 1024;  // links of a tile listed at once (rounds beyond)
+// LDS per workgroup is held to 23040 bytes, so that seven workgroups fit in
+// a CU's 160 KB: 492 list items (on the duct 3-4.5% of the tiles hold more
+// links and take a second round) and two copies of a 16-body force table
+// (with 8 bodies, tiles 64 nodes long often found the table full and sent
+// their sums to global memory)
+constexpr int kLinkCap = 492;   // links of a tile listed at once (rounds beyond)
 constexpr int kRec = 16;        // bodies of a tile with a slot in the LDS force table
-constexpr int kCopies = 4;      // copies of the table's sums (by lane), so fewer lanes add to one address
+constexpr int kCopies = 2;      // copies of the table's sums (by lane), so fewer lanes add to one address
 
 struct FusedLds {
     uint32_t item[kLinkCap];          // link: node << 24 | I << 19 | behind fluid << 18 | owner code of the
-                                      // solid; then, on the in-list path, the link's value (FP32 bits)
+                                      // solid
     uint32_t val[kQ][kBlock];         // population i streamed to node n: val[i][n], as the stored value's
                                       // bits (16-bit storage: zero-extended)
     int key[kRec];                    // owner code of the body in a force slot, -1 free
     unsigned long long sum[kCopies][kRec][6];  // fixed-point F, T of that body
     int wtot[kBlock / 64];
 };
+static_assert(sizeof(FusedLds) <= 23040, "seven workgroups per CU");
 
 // v 2^32 rounded to the nearest integer, ties to even, as a two's-complement
 // 64-bit value.  While |v 2^32| < 2^51 one FP64 add of 1.5 2^52 leaves that
@@ -215,15 +221,19 @@ __device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds &lds, in
     float fa = 0.0f, fb = 0.0f;
     if (exact_q) {
         fa = St::ld(at(src + (size_t)I * Ns, xi));
-        if (behind) fb = St::ld(at(src + (size_t)K * Ns, pull_src_rt(xi, nb_off(x, y, z, nx, ny, nz), K)));
+        if (behind) {
+            // the node behind x, x + c_I (periodic)
+            const uint32_t xb = (uint32_t)(wrap_add(x, dcx(I), nx) + nx * (wrap_add(y, dcy(I), ny) + ny * wrap_add(z, dcz(I), nz)));
+            fb = St::ld(at(src + (size_t)K * Ns, xb));
+        }
     }
     const double *B = sphere ? f.bodies + (size_t)(os - f.n_walls) * kBodyStride : f.wrec + (size_t)os * kBodyStride;
     const LinkGeo g = link_geo(sphere_k(B), exact_q, sphere, a.rho0, x, y, z, nx, ny, nz, I);
     const float vr = St::round(link_value(g.q, fk, fa, fb, behind, g.mw));
     lds.val[I][nl] = St::to_bits(vr);  // a slot no pull is loaded into
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[6];
     const double mom = link_momentum(fk, vr, I, a.rho0);
-    link_force(mom, I, g, acc);
+    link_force_terms(mom, I, g, acc);
     unsigned long long v[6];
     // F = -mom c_I: its fixed-point components are -c M with M = fix(mom)
     // (the rounding is odd-symmetric).  One range test for the four
@@ -404,10 +414,10 @@ __device__ __forceinline__ void finish_value(const FinishArgs &fa, int i)
     if (fa.out2) fa.out2[i] = v;
 }
 
-// Six waves per SIMD: the LDS of a workgroup allows six per CU, and the
-// compiler then keeps the link phase within 80 VGPRs without spilling.
+// Seven waves per SIMD: the LDS of a workgroup allows seven per CU, and the
+// compiler then keeps the kernel within 72 VGPRs without spilling.
 template <int S, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_fused(FusedArgs f)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_fused(FusedArgs f)
 {
     __shared__ FusedLds lds;
     // the previous step's forces, if nobody has read them yet (their sums
@@ -435,7 +445,8 @@ __global__ __launch_bounds__(kBlock) void k_zero_fix(unsigned long long *p, int 
 // tile_begin[m + 1]); XCD k (workgroups k, k + 8, ...) takes its share of
 // the global tile range (runs of neighbouring tiles, by xcd_item) from its
 // own queue, so that each XCD works on neighbouring tiles of the same
-// members while every XCD draws from all of them.
+// members while every XCD draws from all of them.  Six waves per SIMD: its
+// tile loop needs more registers than seven would leave.
 template <int S, int TX, int TY, int TZ>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_batch_fused(BatchStepArgs b)
 {

@@ -71,7 +71,8 @@ __device__ __forceinline__ LinkGeo link_geo(const SphereK &k, bool exact_q, bool
         const float aa = (float)(cx * cx + cy * cy + cz * cz);
         const float cc = (e0 * e0 + e1 * e1 + e2 * e2) - k.R2;
         const float disc = fmaxf(bb * bb - aa * cc, 0.0f);
-        l.q = fminf(fmaxf(cc * __builtin_amdgcn_rcpf(__builtin_sqrtf(disc) - bb), 0.0f), 1.0f);
+        // (the hardware square root and reciprocal, each within 1 ulp)
+        l.q = fminf(fmaxf(cc * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(disc) - bb), 0.0f), 1.0f);
     } else {
         l.q = 0.5f;
     }
@@ -109,20 +110,30 @@ __device__ __forceinline__ double link_momentum(float fk, float vr, int I, float
 }
 
 // Force mom c_K on the body and its torque about the lever arm
-// x_b - X = d - q c_I, added to acc[6] = {F, T} (FP64).  The force is
-// parallel to c_I, so (d - q c_I) x F = d x F: the arm is taken as d.
-__device__ __forceinline__ void link_force(double mom, int I, const LinkGeo &l, double (&acc)[6])
+// x_b - X = d - q c_I, as t[6] = {F, T} (FP64).  The force is parallel to
+// c_I, so (d - q c_I) x F = d x F: the arm is taken as d.
+__device__ __forceinline__ void link_force_terms(double mom, int I, const LinkGeo &l, double (&t)[6])
 {
 #pragma clang fp contract(off)
     const int cx = dcx(I), cy = dcy(I), cz = dcz(I);
     const double a0 = l.d0, a1 = l.d1, a2 = l.d2;
     const double F0 = -mom * cx, F1 = -mom * cy, F2 = -mom * cz;
-    acc[0] += F0;
-    acc[1] += F1;
-    acc[2] += F2;
-    acc[3] += a1 * F2 - a2 * F1;
-    acc[4] += a2 * F0 - a0 * F2;
-    acc[5] += a0 * F1 - a1 * F0;
+    t[0] = F0;
+    t[1] = F1;
+    t[2] = F2;
+    t[3] = a1 * F2 - a2 * F1;
+    t[4] = a2 * F0 - a0 * F2;
+    t[5] = a0 * F1 - a1 * F0;
+}
+
+// The same terms added to acc[6].
+__device__ __forceinline__ void link_force(double mom, int I, const LinkGeo &l, double (&acc)[6])
+{
+#pragma clang fp contract(off)
+    double t[6];
+    link_force_terms(mom, I, l, t);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] += t[c];
 }
 
 // Exclusive prefix of `cnt` (0 <= cnt < 64) over the workgroup and the total

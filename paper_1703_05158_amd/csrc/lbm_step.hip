@@ -227,8 +227,8 @@ __device__ __forceinline__ void collide_adjoint(const StepArgs &a, const float (
             Pi[p][q] = S[p][q] - (p == q ? rd * (1.0f / 3.0f) : 0.f) - rho * u[p] * u[q];
             Q += Pi[p][q] * Pi[p][q];
         }
-    const float s = sqrtf(Q);
-    const float Rr = a.tau0 * a.tau0 + a.smag_k * s * ir, sR = sqrtf(Rr);
+    const float s = __builtin_amdgcn_sqrtf(Q);  // the step's tau* takes the hardware square roots too
+    const float Rr = a.tau0 * a.tau0 + a.smag_k * s * ir, sR = __builtin_amdgcn_sqrtf(Rr);
     const float om = 2.0f / (a.tau0 + sR);
     // adjoints of omega and of the equilibrium / source terms
     float Ob = 0.f;
