@@ -41,6 +41,7 @@ __host__ __device__ constexpr double wgt(int i)
 template <int S> struct Store;
 template <> struct Store<0> {
     using T = float;
+    static __device__ __forceinline__ float cvt(T v) { return v; }  // a stored value as FP32
     static __device__ __forceinline__ float ld(const T *p) { return *p; }
     static __device__ __forceinline__ void st(T *p, float v) { *p = v; }
     static __device__ __forceinline__ void stnt(T *p, float v) { __builtin_nontemporal_store(v, p); }
@@ -52,6 +53,7 @@ template <> struct Store<0> {
 };
 template <> struct Store<1> {
     using T = _Float16;
+    static __device__ __forceinline__ float cvt(T v) { return (float)v; }
     static __device__ __forceinline__ float ld(const T *p) { return (float)*p; }
     static __device__ __forceinline__ void st(T *p, float v) { *p = (_Float16)v; }
     static __device__ __forceinline__ void stnt(T *p, float v) { __builtin_nontemporal_store((_Float16)v, p); }
@@ -64,6 +66,7 @@ template <> struct Store<1> {
 };
 template <> struct Store<2> {  // bfloat16 as raw bits, round to nearest even
     using T = uint16_t;
+    static __device__ __forceinline__ float cvt(T v) { return __uint_as_float((uint32_t)v << 16); }
     static __device__ __forceinline__ float ld(const T *p) { return __uint_as_float((uint32_t)*p << 16); }
     // gfx950's conversion instruction (v_cvt_pk_bf16_f32) rounds to nearest
     // even: one instruction where the rounding in integer arithmetic takes six

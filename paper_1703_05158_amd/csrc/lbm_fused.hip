@@ -216,19 +216,24 @@ __device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds &lds, in
     const uint32_t xi = (uint32_t)(x + nx * (y + ny * z));
     const bool sphere = os >= f.n_walls;
     const bool exact_q = sphere && !f.halfway;
-    // the populations and the solid's record, in one round trip
-    const float fk = St::ld(at(src + (size_t)K * Ns, xi));
-    float fa = 0.0f, fb = 0.0f;
+    // the solid's record and the populations, in one round trip: the record
+    // first, and the populations as stored values, converted only once all
+    // are in flight (a conversion inside a branch would wait for its load,
+    // and for everything issued before it)
+    const double *B = sphere ? f.bodies + (size_t)(os - f.n_walls) * kBodyStride : f.wrec + (size_t)os * kBodyStride;
+    const SphereK sk = sphere_k(B);
+    const T rk = *at(src + (size_t)K * Ns, xi);
+    T ra = T(0), rb = T(0);
     if (exact_q) {
-        fa = St::ld(at(src + (size_t)I * Ns, xi));
+        ra = *at(src + (size_t)I * Ns, xi);
         if (behind) {
             // the node behind x, x + c_I (periodic)
             const uint32_t xb = (uint32_t)(wrap_add(x, dcx(I), nx) + nx * (wrap_add(y, dcy(I), ny) + ny * wrap_add(z, dcz(I), nz)));
-            fb = St::ld(at(src + (size_t)K * Ns, xb));
+            rb = *at(src + (size_t)K * Ns, xb);
         }
     }
-    const double *B = sphere ? f.bodies + (size_t)(os - f.n_walls) * kBodyStride : f.wrec + (size_t)os * kBodyStride;
-    const LinkGeo g = link_geo(sphere_k(B), exact_q, sphere, a.rho0, x, y, z, nx, ny, nz, I);
+    const float fk = St::cvt(rk), fa = St::cvt(ra), fb = St::cvt(rb);
+    const LinkGeo g = link_geo(sk, exact_q, sphere, a.rho0, x, y, z, nx, ny, nz, I);
     const float vr = St::round(link_value(g.q, fk, fa, fb, behind, g.mw));
     lds.val[I][nl] = St::to_bits(vr);  // a slot no pull is loaded into
     double acc[6];
