@@ -216,6 +216,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--static", action="store_true", help="bodies fixed (no per-step re-rasterisation)")
+    ap.add_argument("--path", default="fused", choices=["fused", "split"],
+                    help="step path of the timed lattice: the fused kernel, or the boundary-link pass "
+                         "followed by the pull-collide kernel (same populations bit for bit)")
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
                     help="skip the FP16/BF16 runs and their error against the stored FP64 run")
     ap.add_argument("--no-sweep", dest="sweep", action="store_false",
@@ -258,7 +261,7 @@ def main():
     torch.cuda.set_device(0)
     case = W.case_piston_duct(drift=not args.static)
     K, Wm = args.steps, args.warmup
-    main_run = timed_run(case, args.storage, K, Wm)
+    main_run = timed_run(case, args.storage, K, Wm, args.path)
     copy_gbs = copy_bandwidth()
     main_run["roofline"]["copy_gbs"] = round(copy_gbs, 1)
     main_run["roofline"]["frac_of_copy"] = round(main_run["roofline"]["achieved"] / copy_gbs, 4)
@@ -270,6 +273,7 @@ def main():
         "config": {"workload": "piston_duct_128x128x512_4000spheres" + ("_static" if args.static else "_drift"),
                    "nodes": N, "fluid_nodes": main_run["fluid_nodes"], "spheres": case.n_bodies,
                    "walls": case.n_walls, "tau0": case.tau0, "smag_c": case.smag_c, "storage": args.storage,
+                   "path": args.path,
                    "per_step": "set_bodies_device + step + get_forces_device" if case.drift
                    else "step + get_forces_device"},
         "mflups": main_run["mflups"],
@@ -442,7 +446,7 @@ def sweep_run(steps, warmup=20):
             "speedup": round(t_seq / t_bat, 3)}
 
 
-def timed_run(case, storage, K, Wm):
+def timed_run(case, storage, K, Wm, path="fused"):
     """Warm up, then time K steps of the case (per step: the bodies' table of
     that step handed over on the device, the step, the forces copied into a
     device history); the step kernel is timed with HIP events on its stream."""
@@ -451,7 +455,7 @@ def timed_run(case, storage, K, Wm):
     from paper_1703_05158_amd import Lattice
 
     stream = torch.cuda.current_stream()
-    lat = Lattice.from_case(case, storage=storage, stream=stream.cuda_stream)
+    lat = Lattice.from_case(case, storage=storage, stream=stream.cuda_stream, path=path)
     nb = case.n_bodies
     nbt = nb + case.n_walls
     # per-step kinematics, resident in HBM before timing (the DEM's output)
@@ -540,7 +544,7 @@ def timed_run(case, storage, K, Wm):
     k_avg_s = kms / launches * 1e-3
     achieved = alg_bytes / k_avg_s / 1e9
     step_s = dt / K
-    traffic = measured_traffic(storage, TILE_SHAPES[shape])
+    traffic = measured_traffic(storage, TILE_SHAPES[shape]) if path == "fused" else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
@@ -548,7 +552,7 @@ def timed_run(case, storage, K, Wm):
             "step_achieved": round(alg_bytes / step_s / 1e9, 1),
             "frac_measured": None if traffic is None else round(traffic / k_avg_s / 1e9 / HBM_PEAK_GBS, 4),
             "kernel_mlups": round(N / k_avg_s / 1e6, 1),
-            "kernel": f"k_fused<{storage},{TILE_SHAPES[shape].replace('x', ',')}>",
+            "kernel": f"{'k_fused' if path == 'fused' else 'k_step'}<{storage},{TILE_SHAPES[shape].replace('x', ',')}>",
             "kernel_ms": round(k_avg_s * 1e3, 4),
             "parts_ms_per_step": {k: round(v / launches, 4) for k, v in parts.items()},
             "tile": TILE_SHAPES[shape], "tile_us": {TILE_SHAPES[i]: round(float(t), 1) for i, t in enumerate(shape_us)},
