@@ -248,14 +248,17 @@ lbm_status lbm_get_info(lbm_handle h, lbm_info *info);
 lbm_status lbm_count_fluid(lbm_handle h, int64_t *n_fluid);
 
 /* Timing of the step's parts with HIP events on the handle's stream:
- * lbm_profile(h, 1) starts recording events at the boundaries of the parts
- * of every step (and clears earlier records), lbm_profile(h, 0) stops.
+ * lbm_profile(h, n) with n > 0 starts recording events at the boundaries of
+ * the parts of every n-th step, the first one included (and clears earlier
+ * records); lbm_profile(h, 0) stops.  Each event costs a profiled step a few
+ * microseconds of GPU time, so a sample of the steps disturbs a long run
+ * less.  The fused kernel's start and end are recorded by its own launch.
  * lbm_profile_read synchronises and returns the summed time of the step
  * kernel (the fused kernel, or the pull-collide kernel of the split path) in
  * milliseconds and the number of steps recorded.  lbm_profile_read_parts
  * returns ms[LBM_PROF_PARTS]: the summed time of each part below over the
  * recorded steps (0 for a part the path does not run), and the step count.
- * Errors: ARG, HIP. */
+ * Errors: ARG (n < 0), HIP. */
 enum {
     LBM_PROF_GEOMETRY = 0, /* inflow-plane update and re-rasterisation */
     LBM_PROF_LINKS = 1,    /* boundary-link pass (split path) */

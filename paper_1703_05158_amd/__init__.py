@@ -285,8 +285,9 @@ def lbm_set_state(h, state: bytes) -> None:
     _check(h, _L.lbm_set_state(h, state, len(state)))
 
 
-def lbm_profile(h, enable) -> None:
-    _check(h, _L.lbm_profile(h, int(bool(enable))))
+def lbm_profile(h, every) -> None:
+    """every: False/0 stops; True/1 records every step, n > 1 every n-th."""
+    _check(h, _L.lbm_profile(h, int(every)))
 
 
 def lbm_profile_read(h):
@@ -497,8 +498,8 @@ class Lattice:
     def count_fluid(self):
         return lbm_count_fluid(self.h)
 
-    def profile(self, enable):
-        lbm_profile(self.h, enable)
+    def profile(self, every):
+        lbm_profile(self.h, every)
 
     def profile_read(self):
         return lbm_profile_read(self.h)

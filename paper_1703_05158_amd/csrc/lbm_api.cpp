@@ -83,6 +83,8 @@ struct lbm_ctx {
     int steps_done = 0;
     int64_t device_bytes = 0;
     bool prof = false;
+    int prof_every = 1;                // profile every prof_every-th step
+    int64_t prof_n = 0;                // steps since profiling was switched on
     // profiling: per step, events at the start, after the geometry update,
     // after the link pass (split path), after the step kernel and after the
     // force finish; events come from a pool that lives as long as the handle
@@ -517,7 +519,7 @@ lbm_status build_wall_links(lbm_ctx *h, const uint8_t *wall, int n_walls)
 
 extern "C" {
 
-int32_t lbm_version(void) { return 10200; }
+int32_t lbm_version(void) { return 10300; }
 
 const char *lbm_last_error(lbm_handle h) { return h ? h->err.c_str() : kNullHandle; }
 
@@ -791,13 +793,21 @@ lbm_status step_once(lbm_ctx *h, unsigned long long *fix = nullptr)
 {
     const lbm_config &c = h->cfg;
     std::array<hipEvent_t, 4> ev{};
-    if (h->prof) HIP_TRY(h, prof_mark(h, &ev[0]));
+    // a profiled step: every prof_every-th while profiling is on (each event
+    // costs the step a few microseconds of GPU time)
+    const bool prof = h->prof && (h->prof_n++ % h->prof_every) == 0;
+    if (prof) HIP_TRY(h, prof_mark(h, &ev[0]));
     // the inflow plane's mean velocity is that of the current state, on its
     // own geometry: taken before the spheres of this step are drawn
     if (h->zieb_z >= 0) HIP_TRY(h, launch_zieb_update(c.storage, zieb_args(h), h->stream));
     if (h->dirty) TRY(rasterize_update(h));
-    if (h->prof) HIP_TRY(h, prof_mark(h, &ev[1]));
     if (fix || h->path == LBM_PATH_FUSED) {
+        // profiled: the fused kernel's own start and end (ev[1], ev[3]),
+        // recorded by its launch
+        if (prof) {
+            HIP_TRY(h, prof_event(h, &ev[1]));
+            HIP_TRY(h, prof_event(h, &ev[3]));
+        }
         ev[2] = ev[1];
         FusedArgs f = fused_args(h);
         if (fix) {
@@ -808,16 +818,16 @@ lbm_status step_once(lbm_ctx *h, unsigned long long *fix = nullptr)
             f.fin = pending_finish(h);
             h->fpending = false;
         }
-        HIP_TRY(h, launch_fused(c.storage, f, h->stream));
-        if (h->prof) HIP_TRY(h, prof_mark(h, &ev[3]));
+        HIP_TRY(h, launch_fused(c.storage, f, h->stream, ev[1], ev[3]));
         h->pend = FinishArgs{f.fsum, f.wall_base, h->nb_state, h->n_walls, h->acc, nullptr};
         h->fpending = true;
         if (!fix) h->fcur ^= 1;
     } else {
+        if (prof) HIP_TRY(h, prof_mark(h, &ev[1]));
         TRY(finish_forces(h, nullptr));
         LinkArgs la = link_args(h);
         HIP_TRY(h, launch_links(c.storage, la, h->stream));
-        if (h->prof) HIP_TRY(h, prof_mark(h, &ev[2]));
+        if (prof) HIP_TRY(h, prof_mark(h, &ev[2]));
         // the step kernel's first workgroups add up the wall chunks
         StepArgs a = step_args(h);
         a.n_wsum = la.n_walls;
@@ -826,9 +836,9 @@ lbm_status step_once(lbm_ctx *h, unsigned long long *fix = nullptr)
         a.wsum_wblk = h->wl_wblk;
         a.wsum_out = h->acc;
         HIP_TRY(h, launch_step(c.storage, a, h->stream));
-        if (h->prof) HIP_TRY(h, prof_mark(h, &ev[3]));
+        if (prof) HIP_TRY(h, prof_mark(h, &ev[3]));
     }
-    if (h->prof) h->prof_ev.push_back(ev);
+    if (prof) h->prof_ev.push_back(ev);
     h->cur = 1 - h->cur;
     h->steps_done++;
     return LBM_OK;
@@ -1150,9 +1160,12 @@ lbm_status lbm_profile(lbm_handle h, int32_t enable)
 {
     if (!h) return LBM_ERR_ARG;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (enable < 0) return fail(h, LBM_ERR_ARG, "profile interval %d < 0", enable);
     h->prof_ev.clear();
     h->ev_used = 0;
     h->prof = enable != 0;
+    h->prof_every = enable > 0 ? enable : 1;
+    h->prof_n = 0;
     return LBM_OK;
 }
 

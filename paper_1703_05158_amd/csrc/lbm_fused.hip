@@ -32,6 +32,7 @@
 #include "lbm_internal.h"
 #include "lbm_linkmath.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -515,16 +516,21 @@ __global__ __launch_bounds__(kBlock) void k_batch_flip(int *cur, int n, int *que
 }
 
 template <int S>
-hipError_t launch_fused_s(const FusedArgs &f, hipStream_t s)
+hipError_t launch_fused_s(const FusedArgs &f, hipStream_t s, hipEvent_t start, hipEvent_t stop)
 {
     const dim3 grid(f.s.n_tiles), block(kBlock);
+    void (*k)(FusedArgs) = nullptr;
     switch (f.s.tile) {
-    case kTile64x2x2: hipLaunchKernelGGL((k_fused<S, 64, 2, 2>), grid, block, 0, s, f); break;
-    case kTile32x4x2: hipLaunchKernelGGL((k_fused<S, 32, 4, 2>), grid, block, 0, s, f); break;
-    case kTile32x2x4: hipLaunchKernelGGL((k_fused<S, 32, 2, 4>), grid, block, 0, s, f); break;
-    case kTile16x8x2: hipLaunchKernelGGL((k_fused<S, 16, 8, 2>), grid, block, 0, s, f); break;
+    case kTile64x2x2: k = k_fused<S, 64, 2, 2>; break;
+    case kTile32x4x2: k = k_fused<S, 32, 4, 2>; break;
+    case kTile32x2x4: k = k_fused<S, 32, 2, 4>; break;
+    case kTile16x8x2: k = k_fused<S, 16, 8, 2>; break;
     default: return hipErrorInvalidValue;
     }
+    if (start || stop)
+        hipExtLaunchKernelGGL(k, grid, block, 0, s, start, stop, 0, f);
+    else
+        hipLaunchKernelGGL(k, grid, block, 0, s, f);
     return hipGetLastError();
 }
 
@@ -554,12 +560,12 @@ inline int nblk(long n) { return (int)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
 
-hipError_t launch_fused(int storage, const FusedArgs &f, hipStream_t s)
+hipError_t launch_fused(int storage, const FusedArgs &f, hipStream_t s, hipEvent_t start, hipEvent_t stop)
 {
     switch (storage) {
-    case 0: return launch_fused_s<0>(f, s);
-    case 1: return launch_fused_s<1>(f, s);
-    case 2: return launch_fused_s<2>(f, s);
+    case 0: return launch_fused_s<0>(f, s, start, stop);
+    case 1: return launch_fused_s<1>(f, s, start, stop);
+    case 2: return launch_fused_s<2>(f, s, start, stop);
     default: return hipErrorInvalidValue;
     }
 }

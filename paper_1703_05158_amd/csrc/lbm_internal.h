@@ -185,7 +185,10 @@ struct GeomArgs {
 // storage: 0 = fp32, 1 = fp16, 2 = bf16 deviations
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t s);
 hipError_t launch_links(int storage, const LinkArgs &a, hipStream_t s);
-hipError_t launch_fused(int storage, const FusedArgs &f, hipStream_t s);
+// With start or stop events, the launch records the kernel's own start and
+// end in them (no separate event packets on the stream).
+hipError_t launch_fused(int storage, const FusedArgs &f, hipStream_t s, hipEvent_t start = nullptr,
+                        hipEvent_t stop = nullptr);
 hipError_t launch_finish(const FinishArgs &fa, hipStream_t s);
 hipError_t launch_zero_fix(unsigned long long *p, int n, hipStream_t s);
 

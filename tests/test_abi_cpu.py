@@ -106,7 +106,7 @@ def test_null_handle_and_pointers(P):
 
 
 def test_version(P):
-    assert P.lbm_version() == 10200
+    assert P.lbm_version() == 10300
 
 
 def test_generators_deterministic():

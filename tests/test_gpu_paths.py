@@ -158,6 +158,26 @@ def test_profile_parts(torch_stream):
         lat.close()
 
 
+def test_profile_every_nth_step(torch_stream):
+    """lbm_profile(h, n) records every n-th step, the first included, and
+    rejects a negative interval."""
+    from paper_1703_05158_amd import Lattice, LBMError
+    case = W.case_box(n=(40, 36, 44), n_spheres=4, radius=(2.5, 4.0), v_sigma=0.01, seed=5, drift=True)
+    lat = Lattice.from_case(case, stream=torch_stream)
+    for every, nsteps, want in ((3, 7, 3), (1, 4, 4), (10, 9, 1)):
+        lat.profile(every)
+        for n in range(nsteps):
+            lat.set_bodies(*case.bodies_at(n + 1))
+            lat.step(1)
+        parts, steps = lat.profile_read_parts()
+        assert steps == want
+        assert parts["step"] > 0 and parts["whole"] >= parts["step"]
+    lat.profile(0)
+    with pytest.raises(LBMError):
+        lat.profile(-2)
+    lat.close()
+
+
 def test_forces_read_or_not_give_the_same_state(torch_stream):
     """The step's force sums are finished lazily (by the next fused step, or
     when read).  A handle that reads its forces after every step and one that
