@@ -108,3 +108,73 @@ def test_duct_precision_statement(torch_stream):
                 br, bu, bf = bars[st]
                 assert dr <= br and du <= bu and fe <= bf
         lat.close()
+
+
+def _bf16_nearest_even(x32):
+    """FP32 values rounded to BF16 by the definition of round to nearest,
+    ties to even: of the two BF16 neighbours (the value with its low 16 bits
+    cut, and the next one away from zero) the nearer, on a tie the one whose
+    last kept bit is 0.  Distances in FP64, where they are exact."""
+    u = x32.view(np.uint32).astype(np.uint64)
+    lo = (u >> 16) << 16
+    hi = lo + (1 << 16)
+    as_f = lambda b: b.astype(np.uint32).view(np.float32).astype(np.float64)
+    x, xl, xh = x32.astype(np.float64), as_f(lo), as_f(hi)
+    dl, dh = np.abs(x - xl), np.abs(xh - x)
+    odd = ((lo >> 16) & 1) == 1
+    return np.where((dh < dl) | ((dh == dl) & odd), xh, xl)
+
+
+def _rounding_cases(rng, n):
+    """n FP32 deviations per direction with 2^-30 <= |g| <= 2^-8 (so that
+    g + w rho0 and its difference with w rho0 are exact in FP64 for every
+    weight), mixing random values with the cases rounding decides on:
+    BF16 ties and near-ties, FP16 ties and near-ties in the normal range,
+    and FP16 subnormal ties (odd multiples of 2^-25)."""
+    k = n // 8
+    sign = lambda m: np.where(rng.random(m) < 0.5, -1.0, 1.0)
+    mag = lambda m: rng.uniform(1.0, 2.0, m) * 2.0 ** rng.integers(-30, -8, m)
+    parts = [(sign(2 * k) * mag(2 * k)).astype(np.float32)]
+    base = (sign(k) * mag(k)).astype(np.float32).view(np.uint32)
+    for low in (0x8000, 0x7FFF, 0x8001):  # BF16: tie, just below, just above
+        parts.append(((base & np.uint32(0xFFFF0000)) | np.uint32(low)).view(np.float32))
+    b16 = (sign(k) * rng.uniform(1.0, 2.0, k) * 2.0 ** rng.integers(-14, -8, k)).astype(np.float32).view(np.uint32)
+    for low in (0x1000, 0x0FFF):  # FP16 (13 bits dropped in its normal range): tie, just below
+        parts.append(((b16 & np.uint32(0xFFFFE000)) | np.uint32(low)).view(np.float32))
+    odd = 2 * rng.integers(0, 256, n - 7 * k) + 1  # FP16 subnormal ties
+    parts.append((sign(n - 7 * k) * odd * 2.0 ** -25).astype(np.float32))
+    g = np.concatenate(parts)
+    rng.shuffle(g)
+    return g
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_storage_rounds_to_nearest_even(storage, torch_stream):
+    """R19: a stored deviation is the FP32 deviation rounded to nearest, ties
+    to even (FP16 with subnormals, by numpy's IEEE conversion; BF16 by the
+    definition above; FP32 unchanged).  Populations set through the C ABI
+    and read back give the stored values exactly: with rho0 = 1 and the
+    deviations of _rounding_cases, f = g + w, g = f - w and f' = h + w are all
+    exact in FP64, on the host and in the library."""
+    from paper_1703_05158_amd import Lattice
+    case = W.case_box(n=(16, 16, 16), n_spheres=0, seed=2)
+    lat = Lattice.from_case(case, storage=storage, stream=torch_stream)
+    import oracle
+    c, wt, _ = oracle.tables()
+    w = np.asarray(wt, dtype=np.float64)
+    rng = np.random.Generator(np.random.PCG64(19))
+    N = 16 ** 3
+    g = np.stack([_rounding_cases(rng, N) for _ in range(19)]).reshape(19, 16, 16, 16)
+    f = g.astype(np.float64) + w[:, None, None, None]
+    assert np.array_equal(f - w[:, None, None, None], g.astype(np.float64))
+    lat.set_populations(f)
+    h = lat.get_populations() - w[:, None, None, None]
+    if storage == "f32":
+        want = g.astype(np.float64)
+    elif storage == "f16":
+        want = g.astype(np.float16).astype(np.float64)
+    else:
+        want = _bf16_nearest_even(g.reshape(-1)).reshape(g.shape)
+    bad = np.flatnonzero(h.reshape(-1) != want.reshape(-1))
+    assert bad.size == 0, f"{bad.size} values differ, first: g={g.reshape(-1)[bad[0]]!r} stored={h.reshape(-1)[bad[0]]!r} want={want.reshape(-1)[bad[0]]!r}"
+    lat.close()
