@@ -54,8 +54,7 @@ constexpr int kRec = 16;        // bodies of a tile with a slot in the LDS force
 constexpr int kCopies = 2;      // copies of the table's sums (by lane), so fewer lanes add to one address
 
 struct FusedLds {
-    uint32_t item[kLinkCap];          // link: node << 24 | I << 19 | behind fluid << 18 | owner code of the
-                                      // solid
+    uint32_t item[kLinkCap];          // link: node << 24 | I << 19 | (node behind fluid) << 18
     uint32_t val[kQ][kBlock];         // population i streamed to node n: val[i][n], as the stored value's
                                       // bits (16-bit storage: zero-extended)
     int key[kRec];                    // owner code of the body in a force slot, -1 free
@@ -187,15 +186,6 @@ __device__ __forceinline__ uint32_t pull_src(uint32_t idx, const NbOff &o, int i
     return (uint32_t)((int)idx + d);
 }
 
-// The same for a direction known only at run time.
-__device__ __forceinline__ uint32_t pull_src_rt(uint32_t idx, const NbOff &o, int i)
-{
-    const int cx = dcx(i), cy = dcy(i), cz = dcz(i);
-    const int d = (cx > 0 ? o.xm : (cx < 0 ? o.xp : 0)) + (cy > 0 ? o.ym : (cy < 0 ? o.yp : 0)) +
-                  (cz > 0 ? o.zm : (cz < 0 ? o.zp : 0));
-    return (uint32_t)((int)idx + d);
-}
-
 // Link j of the tile's list: its value into LDS, its momentum into the force
 // table.  Walls are records like spheres: reference point, velocity, no
 // spin, q = 1/2 and no minimum image (their arm is about the reference
@@ -212,9 +202,12 @@ __device__ __forceinline__ void fused_link(const FusedArgs &f, FusedLds &lds, in
     const uint32_t it = lds.item[j];
     const int nl = (int)(it >> 24), I = (int)((it >> 19) & 31u), K = opp(I);
     const bool behind = (it >> 18) & 1u;
-    const int os = (int)(it & 0x7FFFu);  // owner code of the solid node p = x - c_I
     const int x = x0 + nl % TX, y = y0 + (nl / TX) % TY, z = z0 + nl / (TX * TY);
     const uint32_t xi = (uint32_t)(x + nx * (y + ny * z));
+    // owner code of the solid node p = x - c_I (periodic; a cache hit: the
+    // node's own lane loaded it when it listed the link)
+    const int os = *at(a.own, (uint32_t)(wrap_add(x, -dcx(I), nx) +
+                                         nx * (wrap_add(y, -dcy(I), ny) + ny * wrap_add(z, -dcz(I), nz))));
     const bool sphere = os >= f.n_walls;
     const bool exact_q = sphere && !f.halfway;
     // the solid's record and the populations, in one round trip: the record
@@ -332,33 +325,30 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int t, FusedLds &
     if (!any_fluid) return;
 
     // 2. the tile's links, listed and spread over the workgroup, in rounds
-    //    of kLinkCap (the first from the codes in registers, later ones, rare,
-    //    load them again).  A link's value goes into its node's slot of
-    //    lds.val, which no pull is loaded into, so the pulls stay in flight.
-    auto item = [&](int i, uint32_t code) {
-        const uint32_t behind = ((solid >> opp(i)) & 1u) ^ 1u;
-        return ((uint32_t)tid << 24) | ((uint32_t)i << 19) | (behind << 18) | code;
+    //    of kLinkCap.  An item is node << 24 | I << 19 | (the node behind x
+    //    is fluid) << 18; each lane walks only its own cut directions (a
+    //    wavefront's walk is as long as its lanes' largest count, not 18).
+    //    A link's value goes into its node's slot of lds.val, which no pull
+    //    is loaded into, so the pulls stay in flight.
+    // bit i: the pull source of opp(i), x + c_i, is fluid (opp pairs i, i + 9)
+    const uint32_t nsolid = ~solid;
+    const uint32_t behind_bits = ((nsolid >> 9) & 0x3FEu) | ((nsolid << 9) & 0x7FC00u);
+    auto list = [&](int base) {  // the items with list index in [base, base + kLinkCap)
+        uint32_t mm = m;
+        int k = pos - base;
+        while (mm) {
+            const int i = __builtin_ctz(mm);
+            mm &= mm - 1u;
+            if (k >= 0 && k < kLinkCap)
+                lds.item[k] = ((uint32_t)tid << 24) | ((uint32_t)i << 19) | (((behind_bits >> i) & 1u) << 18);
+            ++k;
+        }
     };
-    {
-        int k = pos;
-#pragma unroll
-        for (int i = 1; i < kQ; ++i)
-            if ((m >> i) & 1u) {
-                if (k < kLinkCap) lds.item[k] = item(i, on[i]);
-                ++k;
-            }
-    }
+    list(0);
     for (int base = 0; base < tot; base += kLinkCap) {
         if (base) {
             lds_barrier();  // the previous round's list is processed
-            int k = pos;
-#pragma unroll 1
-            for (int i = 1; i < kQ; ++i)
-                if ((m >> i) & 1u) {
-                    if (k >= base && k < base + kLinkCap)
-                        lds.item[k - base] = item(i, *at(a.own, pull_src_rt(idx, no, i)));
-                    ++k;
-                }
+            list(base);
         }
         lds_barrier();  // the list is written (an LDS-only barrier: the pulls stay in flight)
         const int n = min(kLinkCap, tot - base);
