@@ -248,9 +248,9 @@ lbm_status lbm_get_info(lbm_handle h, lbm_info *info);
 lbm_status lbm_count_fluid(lbm_handle h, int64_t *n_fluid);
 
 /* Timing of the step's parts with HIP events on the handle's stream:
- * lbm_profile(h, n) with n > 0 starts recording events at the boundaries of
- * the parts of every n-th step, the first one included (and clears earlier
- * records); lbm_profile(h, 0) stops.  Each event costs a profiled step a few
+ * lbm_profile(h, every) with every > 0 starts recording events at the
+ * boundaries of the parts of every every-th step, the first one included
+ * (and clears earlier records); lbm_profile(h, 0) stops.  Each event costs a profiled step a few
  * microseconds of GPU time, so a sample of the steps disturbs a long run
  * less.  The fused kernel's start and end are recorded by its own launch.
  * lbm_profile_read synchronises and returns the summed time of the step
@@ -266,7 +266,7 @@ enum {
     LBM_PROF_WHOLE = 3,    /* the whole step, first event to last */
     LBM_PROF_PARTS = 4
 };
-lbm_status lbm_profile(lbm_handle h, int32_t enable);
+lbm_status lbm_profile(lbm_handle h, int32_t every);
 lbm_status lbm_profile_read(lbm_handle h, double *ms_total, int64_t *launches);
 lbm_status lbm_profile_read_parts(lbm_handle h, double *ms, int64_t *steps);
 

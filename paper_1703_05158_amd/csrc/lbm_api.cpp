@@ -1156,15 +1156,15 @@ lbm_status lbm_count_fluid(lbm_handle h, int64_t *n_fluid)
     return LBM_OK;
 }
 
-lbm_status lbm_profile(lbm_handle h, int32_t enable)
+lbm_status lbm_profile(lbm_handle h, int32_t every)
 {
     if (!h) return LBM_ERR_ARG;
+    if (every < 0) return fail(h, LBM_ERR_ARG, "profile interval %d < 0", every);
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    if (enable < 0) return fail(h, LBM_ERR_ARG, "profile interval %d < 0", enable);
     h->prof_ev.clear();
     h->ev_used = 0;
-    h->prof = enable != 0;
-    h->prof_every = enable > 0 ? enable : 1;
+    h->prof = every != 0;
+    h->prof_every = every > 0 ? every : 1;
     h->prof_n = 0;
     return LBM_OK;
 }
