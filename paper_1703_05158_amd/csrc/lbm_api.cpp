@@ -1278,9 +1278,14 @@ lbm_status lbm_drag_gradient(lbm_handle h, int32_t nsteps, int32_t ckpt, double 
     const int nseg = std::min(ckpt, nsteps);
     // device buffers of this call
     std::vector<void *> bufs;
+    bool oom = false;
     auto get = [&](size_t bytes) -> void * {
         void *p = nullptr;
-        if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) return nullptr;
+        if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) {
+            (void)hipGetLastError();  // not left for the next launch to report
+            oom = true;
+            return nullptr;
+        }
         bufs.push_back(p);
         return p;
     };
@@ -1289,6 +1294,19 @@ lbm_status lbm_drag_gradient(lbm_handle h, int32_t nsteps, int32_t ckpt, double 
         for (void *p : bufs) (void)hipFree(p);
         bufs.clear();
     };
+    // every return (an error of a HIP call included) frees the buffers and
+    // leaves profiling as it was
+    const bool prof = h->prof;
+    struct Exit {
+        decltype(release) &free_all;
+        lbm_ctx *h;
+        bool prof;
+        ~Exit()
+        {
+            free_all();
+            h->prof = prof;
+        }
+    } on_exit{release, h, prof};
     std::vector<float *> ck((size_t)nck), seg((size_t)nseg);
     for (auto &b : ck) b = static_cast<float *>(get(popb));
     for (auto &b : seg) b = static_cast<float *>(get(popb));
@@ -1299,24 +1317,15 @@ lbm_status lbm_drag_gradient(lbm_handle h, int32_t nsteps, int32_t ckpt, double 
     double *dF_tile = static_cast<double *>(get(sizeof(double) * 3 * (size_t)h->n_tiles));
     double *dF = static_cast<double *>(get(sizeof(double) * 3));
     double *dV = static_cast<double *>(get(sizeof(double) * 3 * (size_t)std::max(nb, 1)));
-    for (void *p : bufs)
-        if (!p) {
-            release();
-            return fail(h, LBM_ERR_OOM, "no device memory for %d checkpoints and %d recomputed states", nck, nseg);
-        }
+    if (oom) return fail(h, LBM_ERR_OOM, "no device memory for %d checkpoints and %d recomputed states", nck, nseg);
     const lbm_config &c = h->cfg;
     // forward, keeping every ckpt-th state: the steps of lbm_step, so that the
     // state and forces left behind are those of plain stepping
-    const bool prof = h->prof;
     h->prof = false;
     for (int n = 0; n < nsteps; ++n) {
         if (n % ckpt == 0) HIP_TRY(h, hipMemcpyAsync(ck[(size_t)(n / ckpt)], h->pop[h->cur], popb, hipMemcpyDeviceToDevice, h->stream));
         const lbm_status sst = step_once(h);
-        if (sst != LBM_OK) {
-            h->prof = prof;
-            release();
-            return sst;
-        }
+        if (sst != LBM_OK) return sst;
     }
     h->prof = prof;
     TRY(finish_forces(h, nullptr));
@@ -1376,7 +1385,6 @@ lbm_status lbm_drag_gradient(lbm_handle h, int32_t nsteps, int32_t ckpt, double 
     TRY(copy_sync(h, dJdF, dF, sizeof(double) * 3, hipMemcpyDeviceToHost));
     if (nb > 0) TRY(copy_sync(h, dJdV, dV, sizeof(double) * 3 * nb, hipMemcpyDeviceToHost));
     *J = Jv;
-    release();
     return LBM_OK;
 }
 

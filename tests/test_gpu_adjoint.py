@@ -111,6 +111,34 @@ def test_drag_gradient_rejects_unsupported(torch_stream):
     lat.close()
 
 
+def test_drag_gradient_out_of_memory_leaves_the_handle_usable(torch_stream):
+    """A gradient whose checkpoints cannot fit in device memory (300 states
+    of a 256^3 box, 1.27 GB each, about 385 GB) is refused with LBM_ERR_OOM,
+    its buffers are freed, and the handle steps on as before: the state and
+    forces of two steps after the refusal equal those of a handle that never
+    asked (and profiling is left as it was)."""
+    from paper_1703_05158_amd import LBMError, Lattice
+    case = _case(n=(256, 256, 256), n_spheres=4, seed=5)
+    lat = Lattice.from_case(case, stream=torch_stream)
+    ref = Lattice.from_case(case, stream=torch_stream)
+    lat.profile(1)
+    with pytest.raises(LBMError) as e:
+        lat.drag_gradient(300, 1)
+    assert e.value.status == 2  # LBM_ERR_OOM
+    lat.step(2)
+    ref.step(2)
+    _, steps = lat.profile_read_parts()
+    assert steps == 2
+    F, T = lat.get_forces()
+    Fr, Tr = ref.get_forces()
+    assert np.array_equal(F, Fr) and np.array_equal(T, Tr) and np.isfinite(F).all()
+    rho, u = lat.get_macro()
+    rr, ur = ref.get_macro()
+    assert np.array_equal(rho, rr) and np.array_equal(u, ur)
+    lat.close()
+    ref.close()
+
+
 def test_gradient_on_a_32cube_subset_of_the_adjoint_workload(torch_stream):
     """The 96x96x192 drag-gradient workload cut to a 32^3 subset (about its
     sphere density: 5 spheres of radius 4; body force 5e-6 along x, tau0
