@@ -124,10 +124,18 @@ bool finite_all(const double *p, size_t n)
     return true;
 }
 
+// A failed runtime call leaves its code as the last error, which the next
+// kernel launch would report as its own: cleared, the code passed on.
+hipError_t cleared(hipError_t e)
+{
+    if (e != hipSuccess) (void)hipGetLastError();
+    return e;
+}
+
 template <typename T>
 hipError_t dalloc(lbm_ctx *h, T **p, size_t bytes)
 {
-    hipError_t e = hipMalloc((void **)p, bytes ? bytes : 16);
+    hipError_t e = cleared(hipMalloc((void **)p, bytes ? bytes : 16));
     if (e == hipSuccess) h->device_bytes += (int64_t)bytes;
     return e;
 }
@@ -571,10 +579,11 @@ lbm_status lbm_create(const lbm_config *cfg, lbm_handle *out)
         dalloc(h, &h->zpart, sizeof(double) * (3 * kZiebMaxBlocks + 1)) != hipSuccess ||
         dalloc(h, &h->flag, sizeof(int)) != hipSuccess)
         return bail(LBM_ERR_OOM);
-    if (hipHostMalloc((void **)&h->pinned, sizeof(double) * kBodyStride * std::max(c.max_bodies, 1)) != hipSuccess ||
-        hipHostMalloc((void **)&h->forces_pin, sizeof(double) * 6 * std::max(nbt, 1)) != hipSuccess ||
-        hipHostMalloc((void **)&h->order_pin, sizeof(int) * std::max(c.max_bodies, 1)) != hipSuccess ||
-        hipHostMalloc((void **)&h->flag_host, sizeof(int)) != hipSuccess)
+    if (cleared(hipHostMalloc((void **)&h->pinned, sizeof(double) * kBodyStride * std::max(c.max_bodies, 1))) !=
+            hipSuccess ||
+        cleared(hipHostMalloc((void **)&h->forces_pin, sizeof(double) * 6 * std::max(nbt, 1))) != hipSuccess ||
+        cleared(hipHostMalloc((void **)&h->order_pin, sizeof(int) * std::max(c.max_bodies, 1))) != hipSuccess ||
+        cleared(hipHostMalloc((void **)&h->flag_host, sizeof(int))) != hipSuccess)
         return bail(LBM_ERR_OOM);
     if (hipEventCreateWithFlags(&h->stage_evt, hipEventDisableTiming) != hipSuccess) return bail(LBM_ERR_HIP);
     if (hipMemsetAsync(h->wall_map, 0, (size_t)N, h->stream) != hipSuccess ||
@@ -1281,8 +1290,7 @@ lbm_status lbm_drag_gradient(lbm_handle h, int32_t nsteps, int32_t ckpt, double 
     bool oom = false;
     auto get = [&](size_t bytes) -> void * {
         void *p = nullptr;
-        if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) {
-            (void)hipGetLastError();  // not left for the next launch to report
+        if (cleared(hipMalloc(&p, bytes ? bytes : 16)) != hipSuccess) {
             oom = true;
             return nullptr;
         }
@@ -1591,13 +1599,13 @@ lbm_status batch_build(lbm_batch_ctx *b)
         forces += 6 * (h->nb_state + h->n_walls);
         b->gen[(size_t)i] = h->geom_gen;
     }
-    BHIP_TRY(b, hipMalloc((void **)&b->d_members, sizeof(BatchMember) * (size_t)n));
-    if (!b->d_cur) BHIP_TRY(b, hipMalloc((void **)&b->d_cur, sizeof(int) * (size_t)n));
+    BHIP_TRY(b, cleared(hipMalloc((void **)&b->d_members, sizeof(BatchMember) * (size_t)n)));
+    if (!b->d_cur) BHIP_TRY(b, cleared(hipMalloc((void **)&b->d_cur, sizeof(int) * (size_t)n)));
     if (!b->d_queue) {
-        BHIP_TRY(b, hipMalloc((void **)&b->d_queue, sizeof(int) * kQueueInts));
+        BHIP_TRY(b, cleared(hipMalloc((void **)&b->d_queue, sizeof(int) * kQueueInts)));
         BHIP_TRY(b, hipMemsetAsync(b->d_queue, 0, sizeof(int) * kQueueInts, b->stream));
     }
-    if (!b->h_cur) BHIP_TRY(b, hipHostMalloc((void **)&b->h_cur, sizeof(int) * (size_t)n));
+    if (!b->h_cur) BHIP_TRY(b, cleared(hipHostMalloc((void **)&b->h_cur, sizeof(int) * (size_t)n)));
     BHIP_TRY(b, hipMemcpyAsync(b->d_members, hm.data(), sizeof(BatchMember) * (size_t)n, hipMemcpyHostToDevice,
                                b->stream));
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
