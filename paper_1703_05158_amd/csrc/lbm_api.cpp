@@ -510,13 +510,19 @@ lbm_status build_wall_links(lbm_ctx *h, const uint8_t *wall, int n_walls)
         }
         wblk.push_back((int)(blk.size() / 3));
     }
-    h->n_wblk = (int)(blk.size() / 3);
+    const int n_wblk = (int)(blk.size() / 3);
     const int64_t before = h->device_bytes;
-    HIP_TRY(h, dalloc(h, &h->wl_node, sizeof(uint32_t) * nodes.size()));
-    HIP_TRY(h, dalloc(h, &h->wl_blk, sizeof(int) * blk.size()));
-    HIP_TRY(h, dalloc(h, &h->wl_wblk, sizeof(int) * wblk.size()));
-    HIP_TRY(h, dalloc(h, &h->wl_part, sizeof(double) * 6 * (size_t)h->n_wblk));
+    const bool ok = dalloc(h, &h->wl_node, sizeof(uint32_t) * nodes.size()) == hipSuccess &&
+                    dalloc(h, &h->wl_blk, sizeof(int) * blk.size()) == hipSuccess &&
+                    dalloc(h, &h->wl_wblk, sizeof(int) * wblk.size()) == hipSuccess &&
+                    dalloc(h, &h->wl_part, sizeof(double) * 6 * (size_t)n_wblk) == hipSuccess;
     h->wl_bytes = h->device_bytes - before;
+    if (!ok) {
+        // nothing half-made is left for a link pass to read
+        free_wall_links(h);
+        return fail(h, LBM_ERR_OOM, "no device memory for the wall links");
+    }
+    h->n_wblk = n_wblk;
     TRY(copy_sync(h, h->wl_node, nodes.data(), sizeof(uint32_t) * nodes.size(), hipMemcpyHostToDevice));
     TRY(copy_sync(h, h->wl_blk, blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice));
     TRY(copy_sync(h, h->wl_wblk, wblk.data(), sizeof(int) * wblk.size(), hipMemcpyHostToDevice));
