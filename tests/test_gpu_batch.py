@@ -212,3 +212,65 @@ def test_batch_refuses_members_changed_after_build(torch_stream):
         b.close()
         a.close()
         c.close()
+
+
+def test_sweep_at_full_size(torch_stream):
+    """The 48-instance parameter sweep at its full size (76.5 M nodes; boxes
+    of 64^3 to 160x128x128 with up to 1500 static spheres, each with its own
+    tau0, C and body force) stepped as one batch in the launch configuration
+    the bench times: the autotuned batch tile, two one-step graph replays,
+    then one replay of the 50-step graph.  Every instance equals, bit for
+    bit, the same instance stepped alone; the first instance of each box
+    size meets its FP64 oracle run after two steps, and the three 64^3
+    instances with the most spheres after all 52 (populations 1e-5
+    relative, forces and torques 1e-4 norm-relative)."""
+    import oracle
+    from paper_1703_05158_amd import TILE_SHAPES, Batch, Lattice
+    from ._pair import force_rel_err, pop_rel_err
+    cases = W.case_sweep_instances()
+    assert len(cases) == 48
+    first = {}
+    for i, c in enumerate(cases):
+        first.setdefault((c.nx, c.ny, c.nz), i)
+    assert len(first) == 5
+    small = sorted((i for i, c in enumerate(cases) if c.nx == 64), key=lambda i: -cases[i].n_bodies)[:3]
+    batched = [Lattice.from_case(c, stream=torch_stream) for c in cases]
+    single = [Lattice.from_case(c, stream=torch_stream) for c in cases]
+    b = Batch(batched, stream=torch_stream)
+    shape, _ = b.autotune(trial_steps=3)
+    print(f"batch tile {TILE_SHAPES[shape]}")
+
+    def check(i, o, done):
+        pe = pop_rel_err(o, batched[i])
+        fe, te = force_rel_err(o, batched[i])
+        c = cases[i]
+        print(f"instance {i} ({c.nx}x{c.ny}x{c.nz}, {c.n_bodies} spheres) after {done}: "
+              f"pop {pe:.2e} F {fe:.2e} T {te:.2e}", flush=True)
+        assert pe <= 1e-5 and fe <= 1e-4 and te <= 1e-4
+
+    b.step(2)
+    keep = {}
+    for i in sorted(set(first.values()) | set(small)):
+        o = oracle.Oracle.from_case(cases[i])
+        o.step(2)
+        if i in first.values():
+            check(i, o, 2)
+        if i in small:
+            keep[i] = o
+    b.step(50)
+    for i, o in keep.items():
+        o.step(50)
+        check(i, o, 52)
+    del keep
+    for lat in single:
+        lat.step(2)
+        lat.step(50)
+    for s, t in zip(single, batched):
+        assert t.info()["steps_done"] == s.info()["steps_done"] == 52
+        assert np.array_equal(s.get_populations(), t.get_populations())
+        Fs, Ts = s.get_forces()
+        Ft, Tt = t.get_forces()
+        assert np.array_equal(Fs, Ft) and np.array_equal(Ts, Tt)
+    b.close()
+    for lat in single + batched:
+        lat.close()
