@@ -177,3 +177,75 @@ def test_gradient_on_a_32cube_subset_of_the_adjoint_workload(torch_stream):
         fd = (J_of(Vp) - J_of(Vm)) / (2 * h)
         print(f"dJ/dV[{b},{a}] {gV[b, a]:.6e} fd {fd:.6e}")
         assert gV[b, a] == pytest.approx(fd, rel=2e-3, abs=2e-3 * np.max(np.abs(gV)))
+
+
+def test_adjoint_workload_at_full_size(torch_stream):
+    """The drag-gradient workload at its full size (96x96x192, 300 spheres
+    of radius 4, body force 5e-6 along x, 200 steps) in the bench's launch
+    configuration (a checkpoint every 20 steps), checked by what holds at
+    any size: J equals, bit for bit, the summed x-force after a plain
+    forward run of 200 steps, whose final state the gradient leaves behind;
+    a checkpoint every 50 steps gives the same J and gradients to 1e-5; and
+    central differences of J run forward on the GPU agree with the gradient
+    along its own direction (h = 1e-4 on the unit vector of dJ/dV), in
+    dJ/dF_x (h = 5e-8, 1% of the force) and in the three largest components
+    of dJ/dV (h = 1e-4), to 1e-3 (the FP32 gradient's bar against the FP64
+    reference; measured 3e-5 to 1e-4)."""
+    from paper_1703_05158_amd import Lattice
+    case = W.case_adjoint()
+    steps, ckpt = 200, 20
+    nb = case.n_bodies
+
+    def J_of(V=None, F=None):
+        c = case
+        if V is not None:
+            c = dataclasses.replace(c, V=V)
+        if F is not None:
+            c = dataclasses.replace(c, body_force=F)
+        lat = Lattice.from_case(c, stream=torch_stream)
+        lat.step(steps)
+        Fo, To = lat.get_forces()
+        P = lat.get_populations() if V is None and F is None else None
+        lat.close()
+        return float(Fo[:nb, 0].sum()), (Fo, To, P)
+
+    J_fwd, (F_ref, T_ref, P_ref) = J_of()
+    lat = Lattice.from_case(case, stream=torch_stream)
+    J, gF, gV = lat.drag_gradient(steps, ckpt)
+    assert lat.info()["steps_done"] == steps
+    assert np.array_equal(lat.get_populations(), P_ref)
+    F1, T1 = lat.get_forces()
+    assert np.array_equal(F1, F_ref) and np.array_equal(T1, T_ref)
+    lat.close()
+    del P_ref
+    print(f"J {J:.12e} forward {J_fwd:.12e}  dJ/dF {gF}  |dJ/dV| {np.linalg.norm(gV):.6e}")
+    assert J == J_fwd
+
+    lat = Lattice.from_case(case, stream=torch_stream)
+    J50, gF50, gV50 = lat.drag_gradient(steps, 50)
+    lat.close()
+    assert J50 == J
+    assert _rel(gF50, gF) < 1e-5 and _rel(gV50, gV) < 1e-5
+
+    h = 1e-4
+    d = gV / np.linalg.norm(gV)
+    fd = (J_of(V=case.V + h * d)[0] - J_of(V=case.V - h * d)[0]) / (2 * h)
+    print(f"along dJ/dV: {np.linalg.norm(gV):.6e} fd {fd:.6e}")
+    assert fd == pytest.approx(np.linalg.norm(gV), rel=1e-3)
+
+    hF = 5e-8
+    Fp, Fm = np.array(case.body_force, float), np.array(case.body_force, float)
+    Fp[0] += hF
+    Fm[0] -= hF
+    fd = (J_of(F=tuple(Fp))[0] - J_of(F=tuple(Fm))[0]) / (2 * hF)
+    print(f"dJ/dF_x {gF[0]:.6e} fd {fd:.6e}")
+    assert gF[0] == pytest.approx(fd, rel=1e-3)
+
+    for k in np.argsort(-np.abs(gV).ravel())[:3]:
+        b, a = divmod(int(k), 3)
+        Vp, Vm = case.V.copy(), case.V.copy()
+        Vp[b, a] += h
+        Vm[b, a] -= h
+        fd = (J_of(V=Vp)[0] - J_of(V=Vm)[0]) / (2 * h)
+        print(f"dJ/dV[{b},{a}] {gV[b, a]:.6e} fd {fd:.6e}")
+        assert gV[b, a] == pytest.approx(fd, rel=1e-3)
