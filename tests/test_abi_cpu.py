@@ -139,3 +139,41 @@ def test_duct_recipe():
     hi = c.X + c.R[:, None]
     assert lo[:, :2].min() >= 2 - 1e-12 and hi[:, :2].max() <= 46 + 1e-12
     assert lo[:, 2].min() >= 8 - 1e-12 and hi[:, 2].max() <= 110 + 1e-12
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """The package refuses to import without its built library: there is no
+    other path to the step."""
+    import shutil
+    import sys
+    pkg = tmp_path / "paper_1703_05158_amd"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_1703_05158_amd", "__init__.py"), pkg / "__init__.py")
+    r = subprocess.run([sys.executable, "-c", "import paper_1703_05158_amd"], cwd=tmp_path,
+                       env={**os.environ, "PYTHONPATH": str(tmp_path)}, capture_output=True, text=True)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "is not built" in r.stderr
+
+
+def test_oracle_stays_out_of_the_product():
+    """Nothing in the library, its header or its binding names the oracle, and
+    the bench imports it only in its CPU-baseline leg."""
+    import ast
+    for d in ("paper_1703_05158_amd", "include"):
+        for dirpath, _, files in os.walk(os.path.join(ROOT, d)):
+            for f in files:
+                if f.endswith((".py", ".hip", ".cpp", ".h")):
+                    assert "oracle" not in open(os.path.join(dirpath, f)).read().lower(), f
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    users = []
+    for fn in ast.walk(tree):
+        if isinstance(fn, ast.FunctionDef):
+            for node in ast.walk(fn):
+                if isinstance(node, ast.Import) and any(a.name.split(".")[0] == "oracle" for a in node.names):
+                    users.append(fn.name)
+                if isinstance(node, ast.ImportFrom) and (node.module or "").split(".")[0] == "oracle":
+                    users.append(fn.name)
+    top = [n for n in tree.body if isinstance(n, (ast.Import, ast.ImportFrom))
+           and ("oracle" in [a.name.split(".")[0] for a in n.names] or (getattr(n, "module", "") or "").startswith("oracle"))]
+    assert not top
+    assert users == ["cpu_baseline"]
