@@ -87,9 +87,11 @@ __device__ __forceinline__ void acc_first(float &s, bool &first, float t)
 // that nothing reads (a solid node's populations are never pulled, and a
 // node that turns fluid is refilled).  `fluid` selects the lanes whose
 // values count.
-template <int S>
-__device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g)[kQ], bool fluid, uint32_t idx,
-                                              typename Store<S>::T *__restrict__ dst)
+// kForce: the lattice has a body force (the Guo source and the half-force
+// velocity shift); without one those terms are zero and are left out.
+template <int S, bool kForce>
+__device__ __forceinline__ void collide_store_f(const StepArgs &a, const float (&g)[kQ], bool fluid, uint32_t idx,
+                                                typename Store<S>::T *__restrict__ dst)
 {
     using St = Store<S>;
     const size_t Ns = (size_t)a.Ns;
@@ -118,9 +120,9 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g
     }
     const float rho = a.rho0 + rd;
     const float ir = __builtin_amdgcn_rcpf(rho);
-    const float ux = (jx + 0.5f * a.fx) * ir;
-    const float uy = (jy + 0.5f * a.fy) * ir;
-    const float uz = (jz + 0.5f * a.fz) * ir;
+    const float ux = (kForce ? jx + 0.5f * a.fx : jx) * ir;
+    const float uy = (kForce ? jy + 0.5f * a.fy : jy) * ir;
+    const float uz = (kForce ? jz + 0.5f * a.fz : jz) * ir;
     // second moment of f - feq
     const float third = 1.0f / 3.0f;
     const float pxx = sxx - rd * third - rho * ux * ux;
@@ -148,7 +150,7 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g
     const float om1 = 1.0f - om;
     const float cf = 1.0f - 0.5f * om;
     const float uu = ux * ux + uy * uy + uz * uz;
-    const float uF = ux * a.fx + uy * a.fy + uz * a.fz;
+    const float uF = kForce ? ux * a.fx + uy * a.fy + uz * a.fz : 0.0f;
     if (a.flag && fluid && !(rho > 0.f && isfinite(uu))) atomicOr(a.flag, 1);
     // Post-collision deviation of direction i with weight w, for the pair
     // (i, i+9), c = c_i:
@@ -159,7 +161,7 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g
     // even part is shared by i and i+9, the odd part changes sign.  Factors
     // are taken per weight class (1/18 for the axis pairs, 1/36 for the
     // diagonal ones).
-    const float A = om * (rd - 1.5f * rho * uu) - 3.0f * cf * uF;
+    const float A = kForce ? om * (rd - 1.5f * rho * uu) - 3.0f * cf * uF : om * (rd - 1.5f * rho * uu);
     const float B = 4.5f * om * rho, D = 3.0f * om * rho;
     const float w1 = (float)wgt(1), w2 = (float)wgt(4);
     const float a1 = w1 * A, a2 = w2 * A, b1 = w1 * B, b2 = w2 * B, d1 = w1 * D, d2 = w2 * D;
@@ -170,13 +172,29 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g
     for (int i = 1; i <= 9; ++i) {
         const bool axis = wgt(i) == wgt(1);
         const float cu = cdot(CX[i], CY[i], CZ[i], ux, uy, uz);
-        const float cF = cdot(CX[i], CY[i], CZ[i], a.fx, a.fy, a.fz);
-        const float ev = (axis ? a1 : a2) + cu * ((axis ? b1 : b2) * cu + (axis ? e1 : e2) * cF);
-        const float od = (axis ? d1 : d2) * cu + (axis ? o1 : o2) * cF;
+        float ev, od;
+        if (kForce) {
+            const float cF = cdot(CX[i], CY[i], CZ[i], a.fx, a.fy, a.fz);
+            ev = (axis ? a1 : a2) + cu * ((axis ? b1 : b2) * cu + (axis ? e1 : e2) * cF);
+            od = (axis ? d1 : d2) * cu + (axis ? o1 : o2) * cF;
+        } else {
+            ev = (axis ? a1 : a2) + cu * ((axis ? b1 : b2) * cu);
+            od = (axis ? d1 : d2) * cu;
+        }
         const float vp = om1 * g[i] + (ev + od), vm = om1 * g[i + 9] + (ev - od);
         St::stnt(at(dst + (size_t)i * Ns, idx), vp);
         St::stnt(at(dst + (size_t)(i + 9) * Ns, idx), vm);
     }
+}
+
+template <int S>
+__device__ __forceinline__ void collide_store(const StepArgs &a, const float (&g)[kQ], bool fluid, uint32_t idx,
+                                              typename Store<S>::T *__restrict__ dst)
+{
+    if (a.fx != 0.0f || a.fy != 0.0f || a.fz != 0.0f)
+        collide_store_f<S, true>(a, g, fluid, idx, dst);
+    else
+        collide_store_f<S, false>(a, g, fluid, idx, dst);
 }
 
 }  // namespace dev
