@@ -192,3 +192,41 @@ def test_zieb_reduced_precision(torch_stream, storage, pop_bar, rho_bar):
     assert rho == pytest.approx(o.zieb["rho"], rel=rho_bar)
     assert H == pytest.approx(o.zieb["H"], rel=1e-12)
     lat.close()
+
+
+def test_zieb_on_the_full_duct(torch_stream):
+    """The inflow-plane workload the bench times, at its full size: the
+    128x128x512 duct with 4000 drifting spheres, the piston layer held still
+    and the plane z = 1 fed by a virtual cylinder of the duct's cross-section
+    moving at the piston's speed; 3 steps with the sphere table set before
+    each, against the FP64 oracle at the step's bars and the cylinder state
+    to 1e-6."""
+    import dataclasses
+
+    import oracle
+    from paper_1703_05158_amd import Lattice
+    from ._pair import advance
+    oracle.set_threads(16)
+    base = W.case_piston_duct(drift=True)
+    v_piston = float(base.wall_vel[1][2])
+    wv = base.wall_vel.copy()
+    wv[1] = 0.0
+    case = dataclasses.replace(base, wall_vel=wv)
+    area = float((case.wall_id[1] == 0).sum())
+    zp = (1, area, area * case.nz / 2, v_piston)
+    o = oracle.Oracle.from_case(case, init=False)
+    o.set_zieb(*zp)
+    o.init_fields(case.rho_init, case.u_init)
+    lat = Lattice.from_case(case, stream=torch_stream, init=False)
+    lat.set_zieb(*zp)
+    lat.init_fields(case.rho_init, case.u_init)
+    advance(o, lat, case, 0, 3)
+    pe = pop_rel_err(o, lat)
+    fe, te = force_rel_err(o, lat)
+    rho, H, vf = lat.zieb_state()
+    print(f"pop {pe:.2e} F {fe:.2e} T {te:.2e} rho {rho:.10f} (oracle {o.zieb['rho']:.10f}) vf {vf:.3e}")
+    assert pe <= 1e-5 and fe <= 1e-4 and te <= 1e-4
+    assert rho == pytest.approx(o.zieb["rho"], rel=1e-6)
+    assert H == pytest.approx(o.zieb["H"], rel=1e-12)
+    assert vf == pytest.approx(o.zieb["vf"], abs=1e-7)
+    lat.close()
