@@ -170,7 +170,7 @@ __device__ __forceinline__ Node node_of(uint32_t n, int nx, int ny)
 // lane's nodes are loaded kColU at a time across its columns, so that a job
 // waits for few memory round trips.
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_geometry(GeomArgs g)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_geometry(GeomArgs g)
 {
     using St = Store<S>;
     __shared__ uint32_t cand[kColU][kBlock];  // vacate: a lane's leaving nodes, flushed kColU at a time
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_geometry(GeomArgs g)
                 double u0, u1, u2;
                 sphere_velocity(B, v.px, v.py, v.pz, nx, ny, nz, u0, u1, u2);
                 for (int i = 0; i < kQ; ++i)
-                    St::st(pop + (size_t)i * g.Ns + v.n, (float)eq_dev(i, g.rho0, u0, u1, u2));
+                    St::st(at(pop + (size_t)i * g.Ns, v.n), (float)eq_dev(i, g.rho0, u0, u1, u2));
             }
             cnt = 0;
         };
