@@ -102,7 +102,7 @@ __device__ __forceinline__ int wrap_add(int a, int d, int n)
 // neighbouring items share an L2 while every XCD draws from the whole range
 // (a contiguous eighth per XCD loads the XCDs unevenly wherever the work is
 // not spread evenly over the range).  Item i of XCD x's share, in order:
-constexpr int kXcdChunk = 128;
+constexpr int kXcdChunk = 64;
 
 __device__ __forceinline__ int xcd_item(int x, int i) { return ((i / kXcdChunk) * 8 + x) * kXcdChunk + i % kXcdChunk; }
 
